@@ -1,0 +1,248 @@
+"""Seeded synthetic inputs for the RSST step (shared by tests, smoke and bench).
+
+This module holds initial conditions only: grids, seeded random draws, and
+the ideal-gas conversion of (rho, V, P) point values at cell centres to the
+conservative state (rho, rho V, E) with E = P/(gamma-1) + rho|V|^2/2.  It
+contains none of the time-step arithmetic, and imports neither the oracle
+nor the GPU library.
+
+Every field is a float64 numpy array laid out [nvar][nz][ny][nx] (x fastest),
+nvar = ndim + 2, variables (rho, rho V_1..rho V_ndim, E).  A parameter dict
+(`cfg`) carries ndim, n, dx, gamma, xi, cfl, dt_rule, g, bc_lo, bc_hi, form.
+
+Workloads (all in the paper's regime of low Mach number and large density
+contrast; the paper's own test problems are defined in its Sec. 4):
+  wave1d      1D periodic sound + entropy wave (linear analysis, Sec. 2.1/3.1)
+  bubble2d    2D periodic advected dense bubble, contrast 10, Mach 0.01
+  strat3d     3D stratified polytropic box, contrast 100, gravity, walls in z
+  batch2d     many 2D stratified boxes of uneven size, contrast and xi
+  adjoint2d   2D bubble with density noise, for gradients
+  random      smooth random states with small-scale noise, for parity
+Seeds are 20181211 + k.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+GAMMA = 5.0 / 3.0
+SEED0 = 20181211
+
+
+def seed(k: int) -> int:
+    return SEED0 + k
+
+
+def conservative(rho, vel, P, gamma=GAMMA) -> np.ndarray:
+    """Stack (rho, rho V_i, E) from point values; vel is a list of arrays."""
+    rho = np.asarray(rho, dtype=np.float64)
+    comps = [rho]
+    ke = np.zeros_like(rho)
+    for v in vel:
+        v = np.broadcast_to(np.asarray(v, dtype=np.float64), rho.shape)
+        comps.append(rho * v)
+        ke = ke + v * v
+    E = np.asarray(P, dtype=np.float64) / (gamma - 1.0) + 0.5 * rho * ke
+    comps.append(E)
+    return np.ascontiguousarray(np.stack(comps))
+
+
+def base_cfg(ndim, n, *, xi=1.0, form="pvs", bc_lo=None, bc_hi=None, g=None,
+             length=None, gamma=GAMMA, cfl=0.4, dt_rule=0) -> dict:
+    n = list(n)
+    length = list(length) if length is not None else [1.0] * ndim
+    bc_lo = list(bc_lo) if bc_lo is not None else ["periodic"] * ndim
+    bc_hi = list(bc_hi) if bc_hi is not None else list(bc_lo)
+    g = list(g) if g is not None else [0.0] * ndim
+    return {
+        "ndim": ndim,
+        "n": n + [1] * (3 - ndim),
+        "dx": [length[d] / n[d] for d in range(ndim)] + [1.0] * (3 - ndim),
+        "gamma": gamma, "xi": float(xi), "cfl": cfl, "dt_rule": dt_rule,
+        "g": g + [0.0] * (3 - ndim),
+        "bc_lo": bc_lo + ["periodic"] * (3 - ndim),
+        "bc_hi": bc_hi + ["periodic"] * (3 - ndim),
+        "form": form,
+    }
+
+
+def centres(cfg: dict, d: int) -> np.ndarray:
+    return (np.arange(cfg["n"][d]) + 0.5) * cfg["dx"][d]
+
+
+# --------------------------------------------------------------- 1D wave
+
+def wave1d(xi=1.0, form="pvs", n=256, eps=1e-4):
+    """Right-going RSST sound wave plus a static entropy wave, one wavelength.
+
+    rho0 = P0 = 1.  Sound: drho = eps sin kx, dP = a0^2 drho,
+    dV = xi a0 drho / rho0 (the RSST sound eigenvector: the velocity
+    amplitude is xi times the Euler one).  Entropy: drho = eps cos kx.
+    Runs to t_end = 2 xi L / a0, two crossings at the reduced speed a0/xi.
+    """
+    cfg = base_cfg(1, [n], xi=xi, form=form)
+    x = centres(cfg, 0)
+    k = 2 * math.pi
+    a0 = math.sqrt(GAMMA)
+    ds = eps * np.sin(k * x)
+    de = eps * np.cos(k * x)
+    rho = 1.0 + ds + de
+    P = 1.0 + a0 * a0 * ds
+    V = xi * a0 * ds
+    U = conservative(rho, [V], P)
+    meta = {"t_end": 2.0 * xi / a0, "a0": a0, "eps": eps, "k": k}
+    return cfg, U, meta
+
+
+# --------------------------------------------------------------- 2D bubble
+
+def _bubble_prims(n, xi, rng, *, contrast=10.0, mach=0.01, vnoise=1e-5):
+    cfg = base_cfg(2, [n, n], xi=xi)
+    x = centres(cfg, 0)[None, :]
+    y = centres(cfg, 1)[:, None]
+    r = np.sqrt((x - 0.5) ** 2 + (y - 0.5) ** 2)
+    w = 4.0 * cfg["dx"][0]
+    rho = 1.0 + (contrast - 1.0) * 0.5 * (1.0 - np.tanh((r - 0.125) / w))
+    a_bub = math.sqrt(GAMMA / contrast)
+    v0 = mach * a_bub
+    vx = v0 + vnoise * rng.uniform(-1.0, 1.0, size=(n, n))
+    vy = vnoise * rng.uniform(-1.0, 1.0, size=(n, n))
+    P = np.ones((n, n))
+    return cfg, rho, vx, vy, P, v0
+
+
+def bubble2d(n=512, xi=20.0, form="pvs"):
+    """Dense bubble (contrast 10, tanh edge 4 cells) advected at Mach 0.01 of
+    the bubble's sound speed, uniform P = 1, velocity noise 1e-5.
+    Background for the FP32-perturbation form: the uniform ambient state."""
+    rng = np.random.default_rng(seed(2))
+    cfg, rho, vx, vy, P, v0 = _bubble_prims(n, xi, rng)
+    cfg["form"] = form
+    U = conservative(rho, [vx, vy], P)
+    bg = conservative(np.ones(1), [np.full(1, v0), np.zeros(1)], np.ones(1))  # [nv][1]
+    return cfg, U, {"bg": bg, "bg_axis": -1, "v0": v0}
+
+
+# --------------------------------------------------------------- stratified
+
+def polytrope(z, contrast=100.0, delta=1e-4, g=1.0):
+    """Polytropic hydrostatic layer P = rho T on z in [0,1], gravity g along -z.
+
+    Index m = 1/(nabla_ad + delta) - 1 with nabla_ad = (gamma-1)/gamma,
+    T(z) = T_bot - g z/(m+1), T_bot chosen so rho(0)/rho(1) = contrast,
+    rho = (T/T_bot)^m, rho(0) = 1."""
+    nab = (GAMMA - 1.0) / GAMMA
+    m = 1.0 / (nab + delta) - 1.0
+    T_bot = g / ((m + 1.0) * (1.0 - contrast ** (-1.0 / m)))
+    T = T_bot - g * z / (m + 1.0)
+    rho = (T / T_bot) ** m
+    return rho, rho * T
+
+
+def strat3d(n=256, xi=30.0, form="pvs", nz=None, ny=None):
+    """3D stratified box: polytrope along z (contrast 100, delta 1e-4, g = 1
+    along -z), walls in z, periodic in x and y, V = 0, pressure noise
+    P <- P (1 + 1e-3 U(-1,1)).  Background: the unperturbed polytrope."""
+    nz = nz or n
+    ny = ny or n
+    cfg = base_cfg(3, [n, ny, nz], xi=xi, form=form,
+                   bc_lo=["periodic", "periodic", "reflect"], g=[0.0, 0.0, -1.0])
+    z = centres(cfg, 2)
+    rho0, P0 = polytrope(z)
+    rng = np.random.default_rng(seed(3))
+    noise = rng.uniform(-1.0, 1.0, size=(nz, ny, n))
+    rho = np.broadcast_to(rho0[:, None, None], (nz, ny, n))
+    P = P0[:, None, None] * (1.0 + 1e-3 * noise)
+    zero = np.zeros((nz, ny, n))
+    U = conservative(rho, [zero, zero, zero], P)
+    bg = conservative(rho0, [np.zeros(nz)] * 3, P0)  # [nv][nz]
+    return cfg, U, {"bg": bg, "bg_axis": 2}
+
+
+def strat2d_box(n, contrast, xi, rng, form="pvs"):
+    """One 2D stratified box: polytrope along -y, walls in y, periodic in x."""
+    cfg = base_cfg(2, [n, n], xi=xi, form=form, bc_lo=["periodic", "reflect"],
+                   g=[0.0, -1.0])
+    y = centres(cfg, 1)
+    rho0, P0 = polytrope(y, contrast=contrast)
+    noise = rng.uniform(-1.0, 1.0, size=(n, n))
+    rho = np.broadcast_to(rho0[:, None], (n, n))
+    P = P0[:, None] * (1.0 + 1e-3 * noise)
+    zero = np.zeros((n, n))
+    U = conservative(rho, [zero, zero], P)
+    bg = conservative(rho0, [np.zeros(n)] * 2, P0)
+    return cfg, U, {"bg": bg, "bg_axis": 1}
+
+
+def batch2d(nbox=512, nmin=64, nmax=256, form="pvs"):
+    """Boxes with N ~ U{nmin..nmax}, contrast ~ logU[3,100], xi ~ logU[1,50],
+    drawn in that order for all boxes, then each box's pressure noise."""
+    rng = np.random.default_rng(seed(4))
+    ns = rng.integers(nmin, nmax + 1, size=nbox)
+    contrast = np.exp(rng.uniform(math.log(3.0), math.log(100.0), size=nbox))
+    xis = np.exp(rng.uniform(0.0, math.log(50.0), size=nbox))
+    boxes = []
+    for b in range(nbox):
+        boxes.append(strat2d_box(int(ns[b]), float(contrast[b]), float(xis[b]), rng, form))
+    return boxes
+
+
+# --------------------------------------------------------------- adjoint
+
+def adjoint2d(n=256, xi=10.0, form="pvs", ndir=32):
+    """Bubble as bubble2d with xi = 10 plus density noise rho <- rho (1 + 1e-5 U)
+    (breaks exact limiter ties of flat regions), and ndir smooth unit-max
+    directions for the initial density (Fourier modes |k| <= 4, N(0,1))."""
+    rng = np.random.default_rng(seed(5))
+    cfg, rho, vx, vy, P, v0 = _bubble_prims(n, xi, rng)
+    cfg["form"] = form
+    rho_clean = rho.copy()
+    rho = rho * (1.0 + 1e-5 * rng.uniform(-1.0, 1.0, size=rho.shape))
+    x = centres(cfg, 0)[None, :]
+    y = centres(cfg, 1)[:, None]
+    dirs = np.zeros((ndir, n, n))
+    for q in range(ndir):
+        f = np.zeros((n, n))
+        for kx in range(-4, 5):
+            for ky in range(-4, 5):
+                a, b = rng.standard_normal(2)
+                ph = 2 * math.pi * (kx * x + ky * y)
+                f += a * np.cos(ph) + b * np.sin(ph)
+        dirs[q] = f / np.abs(f).max()
+    U = conservative(rho, [vx, vy], P)
+    U_clean = conservative(rho_clean, [vx, vy], P)
+    return cfg, U, {"rho": rho, "vx": vx, "vy": vy, "P": P, "dirs": dirs,
+                    "U_clean": U_clean}
+
+
+# --------------------------------------------------------------- random
+
+def random_state(ndim, n, *, seed_k=100, xi=3.0, form="pvs", bc_lo=None, bc_hi=None,
+                 g=None, mach=0.3, drho=0.5, dP=0.3, white=0.02, length=None):
+    """Smooth random admissible state plus small white noise (exercises every
+    limiter branch).  rho in about [1-drho, 1+drho], P about 1 +- dP, |V|
+    about mach * a."""
+    rng = np.random.default_rng(seed(seed_k))
+    cfg = base_cfg(ndim, n, xi=xi, form=form, bc_lo=bc_lo, bc_hi=bc_hi, g=g, length=length)
+    shape = tuple(reversed(list(n)))
+    grids = np.meshgrid(*[centres(cfg, d) / (cfg["dx"][d] * cfg["n"][d])
+                          for d in reversed(range(ndim))], indexing="ij")
+    # grids[q] varies along axis ndim-1-q
+
+    def smooth():
+        f = np.zeros(shape)
+        for _ in range(4):
+            ph = rng.uniform(0, 2 * math.pi)
+            arg = ph
+            for q in range(ndim):
+                arg = arg + 2 * math.pi * rng.integers(1, 4) * grids[q]
+            f += rng.uniform(0.5, 1.0) * np.sin(arg)
+        f /= 4.0
+        return f + white * rng.uniform(-1, 1, size=shape)
+
+    rho = 1.0 + drho * smooth()
+    P = 1.0 + dP * smooth()
+    a = np.sqrt(GAMMA * P / rho)
+    vel = [mach * a * smooth() for _ in range(ndim)]
+    return cfg, conservative(rho, vel, P)
