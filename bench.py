@@ -1,0 +1,168 @@
+#!/usr/bin/env python3
+"""Throughput of the RSST time step on one MI355X.
+
+Workload: the 3D stratified convection box, 256^3 cells, FP64, PVS form,
+xi = 30, walls in z with gravity, periodic in x and y (synthetic, seeded).
+A step is one full SSP-RK2 step (both fused stage kernels) on inputs already
+resident in HBM.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gcell-updates/s & HBM GB/s: FP64 plain vs FP32-pert/batched/adjoint, stated err"
+HBM_PEAK_GBS = 8000.0
+GAMMA = 5.0 / 3.0
+
+
+def parity_err(Ug, Uo, ndim):
+    import numpy as np
+    rho = Uo[0]
+    m2 = sum(Uo[1 + d] ** 2 for d in range(ndim))
+    P = (GAMMA - 1) * (Uo[-1] - 0.5 * m2 / rho)
+    a = np.sqrt(GAMMA * np.abs(P) / rho)
+    s = [np.abs(rho).max()] + [np.abs(rho).max() * a.max()] * ndim + [np.abs(Uo[-1]).max()]
+    return max(float(np.abs(Ug[v] - Uo[v]).max() / s[v]) for v in range(ndim + 2))
+
+
+def traffic_from_profile(kernel_tag: str, version: str):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    was taken on this kernel revision; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel_tag}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("version") != version:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build measures one GPU only (the step is single-device; "
+              "multi-GPU domain decomposition is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1812_04135_amd as R
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    cfg, U0, meta = W.strat3d(n=256, xi=30.0, form="pvs")
+    nv, ncell = U0.shape[0], U0[0].size
+    U = torch.from_numpy(U0).to(dev)
+    sol = R.Solver(cfg)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        sol.step(U)
+    torch.cuda.synchronize()
+
+    K = args.steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+    e_start, e_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e_start.record(stream)
+    for q in range(K):
+        ev[q][0].record(stream)
+        sol.stage(U, 1)
+        ev[q][1].record(stream)
+        sol.stage(U, 2)
+        ev[q][2].record(stream)
+    e_end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    total_ms = e_start.elapsed_time(e_end)
+    s1 = sum(ev[q][0].elapsed_time(ev[q][1]) for q in range(K)) / K
+    s2 = sum(ev[q][1].elapsed_time(ev[q][2]) for q in range(K)) / K
+    ms_step = total_ms / K
+    gcell = ncell / (ms_step * 1e-3) / 1e9
+    try:
+        sol.poll()
+        flags = 0
+    except R.RsstError as e:
+        flags = getattr(e, "flags", -1)
+
+    bytes_s1 = 2 * nv * 8 * ncell
+    bytes_s2 = 3 * nv * 8 * ncell
+    ach2 = bytes_s2 / (s2 * 1e-3) / 1e9
+    ach1 = bytes_s1 / (s1 * 1e-3) / 1e9
+    eff = 5 * nv * 8 * ncell / (ms_step * 1e-3) / 1e9
+    version = R.rsst_version()
+    traffic = traffic_from_profile("stage2_strat3d_256_fp64", version)
+
+    out = {
+        "metric": METRIC,
+        "value": round(gcell, 4),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "strat3d: 3D stratified polytropic box 256^3, PVS, xi=30, "
+                               "gravity -z, walls z, periodic x/y, FP64",
+                   "grid": [256, 256, 256], "form": "pvs", "xi": 30.0, "cfl": 0.4},
+        "roofline": {"bound": "hbm", "achieved": round(ach2, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(ach2 / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "stage_kernel<3,2,double> (RK stage 2)",
+                     "alg_bytes_per_launch": bytes_s2, "avg_ms": round(s2, 5)},
+        "stage1": {"avg_ms": round(s1, 5), "achieved_GBs": round(ach1, 1),
+                   "alg_bytes_per_launch": bytes_s1},
+        "effective_GBs_step": round(eff, 1),
+        "wall_s": round(wall, 3),
+        "nonphysical_flags": flags,
+        "library": version,
+    }
+
+    if not args.no_cpu:
+        import oracle
+        # the CPU oracle on a bounded sample: cpu_steps full 256^3 steps from
+        # the initial state, which also gives the GPU error on that sample
+        t0 = time.perf_counter()
+        Uo, _, _ = oracle.run(cfg, U0, args.cpu_steps)
+        cpu_s = time.perf_counter() - t0
+        Ug = torch.from_numpy(U0).to(dev)
+        s = R.Solver(cfg)
+        s.steps(Ug, args.cpu_steps)
+        torch.cuda.synchronize()
+        err = parity_err(Ug.cpu().numpy(), Uo, 3)
+        s.close()
+        out["cpu_baseline"] = {"value": round(ncell * args.cpu_steps / cpu_s / 1e9, 6),
+                               "unit": "Gcell-updates/s", "cores": oracle.threads(),
+                               "kind": "oracle",
+                               "sample": f"{args.cpu_steps} full steps of the 256^3 box "
+                                         f"({cpu_s:.1f} s)"}
+        out["err_vs_oracle"] = {"max_err_over_scale": err, "steps": args.cpu_steps,
+                                "tolerance": 1e-12}
+    sol.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

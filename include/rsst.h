@@ -1,0 +1,143 @@
+/*
+ * rsst.h -- C ABI of the MI355X (gfx950) explicit time step of the
+ * semi-conservative reduced-speed-of-sound technique (RSST) of
+ * Iijima, Hotta & Imada, arXiv:1812.04135.
+ *
+ * One call of rsst_step advances a caller-owned device state by one
+ * second-order SSP Runge-Kutta step (Sec. 4.1 "Numerical method") of the
+ * finite-volume discretisation of the semi-conservative equations:
+ *   - MUSCL reconstruction of the conservative variables with the
+ *     monotonized-central limiter;
+ *   - local Lax-Friedrichs interface flux with c_tot = |V| + a/xi;
+ *   - flux divergence Delta rho, Delta(rho V_i), Delta E   (eq. pvs_dt0);
+ *   - Delta P from those increments                       (eq. pvs_dt_dpr,
+ *     ideal gas: (de/dP)_rho = 1/(gamma-1), (de/drho)_P = 0);
+ *   - the corrected time derivatives of the chosen form:
+ *       PVS (eq. pvs_dt), DVS (App. A.1), PMS (App. A.2), DMS (App. A.3),
+ *       PD (App. A.4), or plain Euler;
+ *   - gravity rho F and rho V.F added after the correction, Delta P
+ *     unchanged (App. B);
+ *   - CFL time step with Courant number cfl and c_tot (Sec. 4.1, item 1).
+ *
+ * Conventions
+ *   - Status codes: 0 = success, negative = error (see rsst_status).  No
+ *     call throws, prints or aborts.
+ *   - Device pointers are HIP device allocations owned by the caller unless
+ *     stated otherwise.  `stream` is a hipStream_t passed as void*; NULL is
+ *     the default stream.
+ *   - Fields are structure-of-arrays [nvar][nz][ny][nx], x fastest,
+ *     nvar = ndim + 2, variables (rho, rho V_1 .. rho V_ndim, E).  Unused
+ *     axes have n = 1.
+ *   - A handle is bound to one device and one state size; it is not
+ *     thread-safe, and calls on one handle must be ordered on one stream.
+ *   - rsst_step enqueues work only: it does not synchronise, allocate or
+ *     copy, so a sequence of steps can be captured in a HIP graph.
+ */
+#ifndef RSST_H
+#define RSST_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum rsst_status {
+  RSST_OK = 0,
+  RSST_E_ARG = -1,          /* invalid argument or configuration            */
+  RSST_E_NOMEM = -2,        /* device allocation failed                     */
+  RSST_E_DEVICE = -3,       /* a HIP runtime call failed                    */
+  RSST_E_UNSUPPORTED = -4,  /* valid but not supported by this build        */
+  RSST_E_NONPHYSICAL = -5   /* rho <= 0, P <= 0 or a non-finite value seen  */
+};
+
+enum rsst_form { RSST_EULER = 0, RSST_PVS = 1, RSST_PMS = 2, RSST_DVS = 3,
+                 RSST_DMS = 4, RSST_PD = 5 };
+enum rsst_bc { RSST_PERIODIC = 0, RSST_REFLECT = 1 };
+enum rsst_prec { RSST_FP64 = 0, RSST_FP32_PERT = 1 };
+
+typedef struct rsst_config {
+  int ndim;          /* 1, 2 or 3                                             */
+  int n[3];          /* cells per axis; axes >= ndim must be 1                */
+  double dx[3];      /* cell widths (> 0) of the used axes                    */
+  double gamma;      /* ratio of specific heats, > 1                          */
+  double xi;         /* reduction rate of the sound speed, >= 1 (App. A.2)    */
+  double cfl;        /* Courant number in (0, 1]; the paper uses 0.4          */
+  int dt_rule;       /* 0: dt = cfl / (max c_tot * sum_d 1/dx_d)
+                        1: dt = cfl * min_d dx_d / max c_tot                  */
+  double g[3];       /* external force per unit mass (App. B)                 */
+  int bc_lo[3];      /* rsst_bc of the low side of each axis                  */
+  int bc_hi[3];      /* rsst_bc of the high side; a periodic side must face a
+                        periodic side                                         */
+  int form;          /* rsst_form                                             */
+  int prec;          /* rsst_prec.  RSST_FP32_PERT stores U1 = U - U0 in FP32
+                        and does all arithmetic in FP64 on U0 + U1            */
+  const double* bg;  /* FP32_PERT only: device FP64 background U0, layout
+                        [nvar][nbg], caller-owned, must outlive the handle    */
+  int bg_axis;       /* -1: U0 uniform (nbg = 1); else the axis it varies on
+                        (nbg = n[bg_axis])                                    */
+  double t_end;      /* > 0: the CFL step is cut so that t never passes t_end;
+                        0: no end time                                        */
+} rsst_config;
+
+typedef struct rsst_solver* rsst_handle;
+
+/* Validates cfg on the host before touching the device (RSST_E_ARG on any
+ * invalid field), then allocates the workspace (stage buffer, reduction
+ * scalars) on the current device.  t starts at 0.  No allocation happens
+ * after this call. */
+int rsst_init(const rsst_config* cfg, void* stream, rsst_handle* out);
+
+/* Sets t = t0 and computes the CFL time step of state U on the device.
+ * rsst_step calls this by itself on the first CFL step; call it again after
+ * writing U from outside. */
+int rsst_prime(rsst_handle h, const void* U, double t0, void* stream);
+
+/* One SSP-RK2 step of U in place:
+ *   U1 = U + dt R(U);   U <- (U + (U1 + dt R(U1))) / 2.
+ * U: device array of nvar * ncell doubles (FP64) or floats (FP32_PERT,
+ * holding U - U0).  dt_fixed > 0 uses that dt for both stages; dt_fixed <= 0
+ * uses the CFL dt of U, computed on the device (no host sync).  Non-physical
+ * states are latched on the device and reported by rsst_poll. */
+int rsst_step(rsst_handle h, void* U, double dt_fixed, void* stream);
+
+/* One Runge-Kutta stage of rsst_step, for callers that schedule or time the
+ * two stages separately.  stage 1: U1 = U + dt R(U) into the library's stage
+ * buffer (U unchanged); stage 2: U <- (U + (U1 + dt R(U1))) / 2, advancing t
+ * and the device CFL dt.  A stage 2 call must follow a stage 1 call on the
+ * same U and dt_fixed; rsst_step(h, U, dt, s) is stage 1 then stage 2.
+ * RSST_E_ARG for any other stage number. */
+int rsst_stage(rsst_handle h, void* U, int stage, double dt_fixed, void* stream);
+
+/* nsteps calls of rsst_step. */
+int rsst_steps(rsst_handle h, void* U, int nsteps, double dt_fixed, void* stream);
+
+/* Synchronises the stream, then returns the time t and the dt the next CFL
+ * step will use. */
+int rsst_get_time(rsst_handle h, double* t, double* dt_next, void* stream);
+
+/* FP64 diagnostics of U, summed over cells in a fixed order (deterministic):
+ * out[0..7] = (sum rho, sum m1, sum m2, sum m3, sum E, sum |m|^2/(2 rho),
+ *              max |V|, max xi |V| / a), sums times the cell volume.
+ * Synchronises the stream. */
+int rsst_diag(rsst_handle h, const void* U, double out[8], void* stream);
+
+/* Synchronises, copies the non-physical flags seen since the last poll into
+ * *flags (bit 0: rho <= 0, bit 1: P <= 0, bit 2: non-finite), clears them,
+ * and returns RSST_E_NONPHYSICAL if any was set. */
+int rsst_poll(rsst_handle h, uint32_t* flags);
+
+/* Frees the workspace.  The caller's arrays are untouched. */
+int rsst_destroy(rsst_handle h);
+
+/* Static string for a status code. */
+const char* rsst_strerror(int status);
+
+/* Library build identifier (kernel revision), for logs. */
+const char* rsst_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSST_H */

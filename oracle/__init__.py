@@ -82,6 +82,7 @@ def _load():
                                         ctypes.c_double]
         lib.ora_run_tangent.restype = ctypes.c_int64
         lib.ora_diag.argtypes = [cp, dp, dp]
+        lib.ora_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -134,6 +135,11 @@ def _field(U: np.ndarray, cfg: dict) -> np.ndarray:
     ncell = int(np.prod(cfg["n"]))
     assert U.size == nv * ncell, (U.shape, nv, ncell)
     return U
+
+
+def threads() -> int:
+    """OpenMP threads used by the oracle's loops."""
+    return int(_load().ora_threads())
 
 
 # ----------------------------------------------------------------- per cell

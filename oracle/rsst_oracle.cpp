@@ -49,6 +49,7 @@
 #include <cstring>
 #include <vector>
 #include <algorithm>
+#include <omp.h>
 
 extern "C" {
 
@@ -411,6 +412,9 @@ static int64_t ssp_rk2(const ora_config* c, S* U, const S& xi, double dt) {
 extern "C" {
 
 int ora_version(void) { return 1; }
+
+// OpenMP threads the oracle's loops use.
+int ora_threads(void) { return omp_get_max_threads(); }
 
 // Primitive recovery of one cell: out = (rho, V1, V2, V3, P, a2, a, |V|, c_tot)
 void ora_prim(int ndim, double gamma, double xi, const double* u, double* out) {

@@ -1,0 +1,232 @@
+"""MI355X (gfx950) explicit time step of the semi-conservative
+reduced-speed-of-sound technique (RSST), arXiv:1812.04135.
+
+Thin ctypes binding of the C ABI in include/rsst.h.  Every step of the path
+runs in the HIP kernels of librsst.so; this module only marshals arguments.
+PyTorch supplies device memory and the current stream.  If the library is
+not built, importing works but every call raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librsst.so")
+
+RSST_OK = 0
+RSST_E_NONPHYSICAL = -5
+FORMS = {"euler": 0, "pvs": 1, "pms": 2, "dvs": 3, "dms": 4, "pd": 5}
+BCS = {"periodic": 0, "reflect": 1}
+PRECS = {"fp64": 0, "fp32_pert": 1}
+
+
+class rsst_config(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int),
+        ("n", ctypes.c_int * 3),
+        ("dx", ctypes.c_double * 3),
+        ("gamma", ctypes.c_double),
+        ("xi", ctypes.c_double),
+        ("cfl", ctypes.c_double),
+        ("dt_rule", ctypes.c_int),
+        ("g", ctypes.c_double * 3),
+        ("bc_lo", ctypes.c_int * 3),
+        ("bc_hi", ctypes.c_int * 3),
+        ("form", ctypes.c_int),
+        ("prec", ctypes.c_int),
+        ("bg", ctypes.c_void_p),
+        ("bg_axis", ctypes.c_int),
+        ("t_end", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded librsst.so; raises if it was not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"librsst.so not built ({LIB_PATH}); run python -m paper_1812_04135_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+        L.rsst_init.argtypes = [ctypes.POINTER(rsst_config), vp, ctypes.POINTER(vp)]
+        L.rsst_prime.argtypes = [vp, vp, ctypes.c_double, vp]
+        L.rsst_step.argtypes = [vp, vp, ctypes.c_double, vp]
+        L.rsst_stage.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double, vp]
+        L.rsst_steps.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double, vp]
+        L.rsst_get_time.argtypes = [vp, dp, dp, vp]
+        L.rsst_diag.argtypes = [vp, vp, dp, vp]
+        L.rsst_poll.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32)]
+        L.rsst_destroy.argtypes = [vp]
+        L.rsst_strerror.argtypes = [ctypes.c_int]
+        L.rsst_strerror.restype = ctypes.c_char_p
+        L.rsst_version.restype = ctypes.c_char_p
+        for name in ("rsst_init", "rsst_prime", "rsst_step", "rsst_stage", "rsst_steps", "rsst_get_time",
+                     "rsst_diag", "rsst_poll", "rsst_destroy"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+class RsstError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {lib().rsst_strerror(code).decode()} ({code})")
+
+
+def _check(code: int, where: str):
+    if code != RSST_OK:
+        raise RsstError(code, where)
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    if hasattr(t, "data_ptr"):
+        assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA tensors"
+        return ctypes.c_void_p(t.data_ptr())
+    return ctypes.c_void_p(int(t))
+
+
+def make_config(cfg: dict, prec: str = "fp64", bg=None, bg_axis: int = -1,
+                t_end: float = 0.0) -> rsst_config:
+    """rsst_config from a plain parameter dict (the keys of the workloads module)."""
+    c = rsst_config()
+    c.ndim = int(cfg["ndim"])
+    n = list(cfg["n"]) + [1] * 3
+    dx = list(cfg["dx"]) + [1.0] * 3
+    g = list(cfg.get("g", [])) + [0.0] * 3
+    lo = list(cfg.get("bc_lo", [])) + ["periodic"] * 3
+    hi = list(cfg.get("bc_hi", [])) + ["periodic"] * 3
+    for d in range(3):
+        c.n[d] = int(n[d]) if d < c.ndim else 1
+        c.dx[d] = float(dx[d])
+        c.g[d] = float(g[d]) if d < c.ndim else 0.0
+        c.bc_lo[d] = BCS[lo[d]] if isinstance(lo[d], str) else int(lo[d])
+        c.bc_hi[d] = BCS[hi[d]] if isinstance(hi[d], str) else int(hi[d])
+    c.gamma = float(cfg["gamma"])
+    c.xi = float(cfg["xi"])
+    c.cfl = float(cfg.get("cfl", 0.4))
+    c.dt_rule = int(cfg.get("dt_rule", 0))
+    f = cfg.get("form", "pvs")
+    c.form = FORMS[f] if isinstance(f, str) else int(f)
+    c.prec = PRECS[prec] if isinstance(prec, str) else int(prec)
+    c.bg = ctypes.c_void_p(bg.data_ptr()) if bg is not None else None
+    c.bg_axis = int(bg_axis)
+    c.t_end = float(t_end)
+    return c
+
+
+# ---- the C ABI, same names -------------------------------------------------
+
+def rsst_init(cfg: rsst_config, stream=None) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(lib().rsst_init(ctypes.byref(cfg), _stream(stream), ctypes.byref(h)), "rsst_init")
+    return h
+
+
+def rsst_prime(h, U, t0: float = 0.0, stream=None):
+    _check(lib().rsst_prime(h, _ptr(U), float(t0), _stream(stream)), "rsst_prime")
+
+
+def rsst_step(h, U, dt_fixed: float = 0.0, stream=None):
+    _check(lib().rsst_step(h, _ptr(U), float(dt_fixed), _stream(stream)), "rsst_step")
+
+
+def rsst_stage(h, U, stage: int, dt_fixed: float = 0.0, stream=None):
+    _check(lib().rsst_stage(h, _ptr(U), int(stage), float(dt_fixed), _stream(stream)), "rsst_stage")
+
+
+def rsst_steps(h, U, nsteps: int, dt_fixed: float = 0.0, stream=None):
+    _check(lib().rsst_steps(h, _ptr(U), int(nsteps), float(dt_fixed), _stream(stream)), "rsst_steps")
+
+
+def rsst_get_time(h, stream=None):
+    t, dt = ctypes.c_double(), ctypes.c_double()
+    _check(lib().rsst_get_time(h, ctypes.byref(t), ctypes.byref(dt), _stream(stream)), "rsst_get_time")
+    return t.value, dt.value
+
+
+def rsst_diag(h, U, stream=None) -> np.ndarray:
+    out = (ctypes.c_double * 8)()
+    _check(lib().rsst_diag(h, _ptr(U), out, _stream(stream)), "rsst_diag")
+    return np.array(out[:], dtype=np.float64)
+
+
+def rsst_poll(h) -> int:
+    """Returns the flag word; raises RsstError(RSST_E_NONPHYSICAL) if any flag is set."""
+    f = ctypes.c_uint32()
+    code = lib().rsst_poll(h, ctypes.byref(f))
+    if code not in (RSST_OK, RSST_E_NONPHYSICAL):
+        _check(code, "rsst_poll")
+    if code == RSST_E_NONPHYSICAL:
+        err = RsstError(code, "rsst_poll")
+        err.flags = f.value
+        raise err
+    return f.value
+
+
+def rsst_destroy(h):
+    _check(lib().rsst_destroy(h), "rsst_destroy")
+
+
+def rsst_version() -> str:
+    return lib().rsst_version().decode()
+
+
+# ---- convenience wrapper ----------------------------------------------------
+
+class Solver:
+    """Owns one rsst handle.  U is a contiguous CUDA tensor [nvar, ...]
+    (float64, or float32 perturbation with prec='fp32_pert' and a float64
+    background tensor bg [nvar, nbg])."""
+
+    def __init__(self, cfg: dict, prec: str = "fp64", bg=None, bg_axis: int = -1,
+                 t_end: float = 0.0, stream=None):
+        self.cfg = dict(cfg)
+        self.prec = prec
+        self._bg = bg  # keep the background alive as long as the handle
+        self._c = make_config(cfg, prec, bg, bg_axis, t_end)
+        self.h = rsst_init(self._c, stream)
+
+    def prime(self, U, t0=0.0, stream=None):
+        rsst_prime(self.h, U, t0, stream)
+
+    def step(self, U, dt_fixed=0.0, stream=None):
+        rsst_step(self.h, U, dt_fixed, stream)
+
+    def stage(self, U, stage, dt_fixed=0.0, stream=None):
+        rsst_stage(self.h, U, stage, dt_fixed, stream)
+
+    def steps(self, U, nsteps, dt_fixed=0.0, stream=None):
+        rsst_steps(self.h, U, nsteps, dt_fixed, stream)
+
+    def time(self, stream=None):
+        return rsst_get_time(self.h, stream)
+
+    def diag(self, U, stream=None):
+        return rsst_diag(self.h, U, stream)
+
+    def poll(self):
+        return rsst_poll(self.h)
+
+    def close(self):
+        if self.h is not None:
+            rsst_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

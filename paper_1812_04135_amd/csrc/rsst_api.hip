@@ -1,0 +1,249 @@
+// C ABI of the RSST step library (declared in include/rsst.h).
+//
+// Host responsibilities only: validate the configuration before any device
+// call, own the workspace (the stage buffer U1, the reduction scalars and the
+// diagnostic partials), and enqueue the kernels of rsst_kernels.hip.  No
+// numerics happen on the host.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+
+#include "rsst.h"
+#include "rsst_internal.h"
+
+using rsstk::Geometry;
+using rsstk::StageArgs;
+
+struct rsst_solver {
+  rsst_config cfg;
+  StageArgs args;
+  int device;
+  int nv;
+  long long ncell;
+  size_t elem;       // bytes per stored value
+  void* u1;          // stage buffer, owned
+  double* scal;      // device scalars, owned
+  double* part;      // diag partials, owned
+  double* diag_out;  // 8 doubles, owned
+  int npart;
+  bool primed;
+};
+
+static int check(hipError_t e) { return e == hipSuccess ? RSST_OK : RSST_E_DEVICE; }
+
+static int validate(const rsst_config* c) {
+  if (!c) return RSST_E_ARG;
+  if (c->ndim < 1 || c->ndim > 3) return RSST_E_ARG;
+  for (int d = 0; d < 3; ++d) {
+    if (d < c->ndim) {
+      if (c->n[d] < 4) return RSST_E_ARG;
+      if (!(c->dx[d] > 0.0) || !std::isfinite(c->dx[d])) return RSST_E_ARG;
+      if (c->bc_lo[d] != RSST_PERIODIC && c->bc_lo[d] != RSST_REFLECT) return RSST_E_ARG;
+      if (c->bc_hi[d] != RSST_PERIODIC && c->bc_hi[d] != RSST_REFLECT) return RSST_E_ARG;
+      if ((c->bc_lo[d] == RSST_PERIODIC) != (c->bc_hi[d] == RSST_PERIODIC)) return RSST_E_ARG;
+      if (!std::isfinite(c->g[d])) return RSST_E_ARG;
+    } else if (c->n[d] != 1) {
+      return RSST_E_ARG;
+    }
+  }
+  if (!(c->gamma > 1.0) || !std::isfinite(c->gamma)) return RSST_E_ARG;
+  if (!(c->xi >= 1.0) || !std::isfinite(c->xi)) return RSST_E_ARG;
+  if (!(c->cfl > 0.0 && c->cfl <= 1.0)) return RSST_E_ARG;
+  if (c->dt_rule != 0 && c->dt_rule != 1) return RSST_E_ARG;
+  if (c->form < RSST_EULER || c->form > RSST_PD) return RSST_E_ARG;
+  if (c->prec != RSST_FP64 && c->prec != RSST_FP32_PERT) return RSST_E_ARG;
+  if (c->prec == RSST_FP32_PERT) {
+    if (!c->bg) return RSST_E_ARG;
+    if (c->bg_axis < -1 || c->bg_axis >= c->ndim) return RSST_E_ARG;
+  }
+  if (!(c->t_end >= 0.0) || !std::isfinite(c->t_end)) return RSST_E_ARG;
+  // supported launch shapes: whole x rows in one workgroup
+  if (c->ndim == 1 && c->n[0] > 1024) return RSST_E_UNSUPPORTED;
+  if (c->ndim == 2 && c->n[0] > 1024) return RSST_E_UNSUPPORTED;
+  if (c->ndim == 3) {
+    if (c->n[0] > 256) return RSST_E_UNSUPPORTED;
+  }
+  return RSST_OK;
+}
+
+extern "C" {
+
+const char* rsst_strerror(int s) {
+  switch (s) {
+    case RSST_OK: return "success";
+    case RSST_E_ARG: return "invalid argument or configuration";
+    case RSST_E_NOMEM: return "device allocation failed";
+    case RSST_E_DEVICE: return "HIP runtime call failed";
+    case RSST_E_UNSUPPORTED: return "configuration not supported by this build";
+    case RSST_E_NONPHYSICAL: return "non-physical state (rho <= 0, P <= 0 or non-finite)";
+    default: return "unknown status";
+  }
+}
+
+const char* rsst_version(void) { return "rsst-gfx950 stage-v1"; }
+
+int rsst_init(const rsst_config* cfg, void* stream, rsst_handle* out) {
+  if (!out) return RSST_E_ARG;
+  *out = nullptr;
+  int st = validate(cfg);
+  if (st != RSST_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+
+  rsst_solver* h = new (std::nothrow) rsst_solver();
+  if (!h) return RSST_E_NOMEM;
+  h->cfg = *cfg;
+  h->nv = cfg->ndim + 2;
+  h->ncell = (long long)cfg->n[0] * cfg->n[1] * cfg->n[2];
+  h->elem = cfg->prec == RSST_FP32_PERT ? sizeof(float) : sizeof(double);
+  if (hipGetDevice(&h->device) != hipSuccess) { delete h; return RSST_E_DEVICE; }
+
+  StageArgs& a = h->args;
+  std::memset(&a, 0, sizeof(a));
+  a.geo = rsstk::plan_geometry(cfg->ndim, cfg->n);
+  a.ncell = h->ncell;
+  for (int d = 0; d < 3; ++d) {
+    a.bc_lo[d] = cfg->bc_lo[d];
+    a.bc_hi[d] = cfg->bc_hi[d];
+    a.inv_dx[d] = d < cfg->ndim ? 1.0 / cfg->dx[d] : 0.0;
+    a.g[d] = d < cfg->ndim ? cfg->g[d] : 0.0;
+  }
+  a.gamma = cfg->gamma;
+  a.gm1 = cfg->gamma - 1.0;
+  a.inv_gm1 = 1.0 / (cfg->gamma - 1.0);
+  a.inv_xi = 1.0 / cfg->xi;
+  a.f = 1.0 - 1.0 / (cfg->xi * cfg->xi);
+  a.form = cfg->form;
+  double hlen;
+  if (cfg->dt_rule == 1) {
+    hlen = cfg->dx[0];
+    for (int d = 1; d < cfg->ndim; ++d) hlen = std::fmin(hlen, cfg->dx[d]);
+  } else {
+    double sum = 0.0;
+    for (int d = 0; d < cfg->ndim; ++d) sum += 1.0 / cfg->dx[d];
+    hlen = 1.0 / sum;
+  }
+  a.cfl_h = cfg->cfl * hlen;
+  a.t_end = cfg->t_end;
+  a.prec = cfg->prec;
+  a.bg = cfg->bg;
+  a.bg_axis = cfg->prec == RSST_FP32_PERT ? cfg->bg_axis : -1;
+  a.nbg = (a.bg_axis >= 0) ? cfg->n[a.bg_axis] : 1;
+
+  h->npart = rsstk::diag_partials(h->ncell);
+  const size_t ubytes = (size_t)h->nv * h->ncell * h->elem;
+  if (hipMalloc(&h->u1, ubytes) != hipSuccess) { delete h; return RSST_E_NOMEM; }
+  if (hipMalloc((void**)&h->scal, rsstk::kNumScalars * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&h->part, (size_t)h->npart * 8 * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&h->diag_out, 8 * sizeof(double)) != hipSuccess) {
+    (void)hipFree(h->u1); (void)hipFree(h->scal); (void)hipFree(h->part); (void)hipFree(h->diag_out);
+    delete h;
+    return RSST_E_NOMEM;
+  }
+  if (hipMemsetAsync(h->scal, 0, rsstk::kNumScalars * sizeof(double), s) != hipSuccess) {
+    rsst_destroy(h);
+    return RSST_E_DEVICE;
+  }
+  a.scal = h->scal;
+  h->primed = false;
+  *out = h;
+  return RSST_OK;
+}
+
+int rsst_prime(rsst_handle h, const void* U, double t0, void* stream) {
+  if (!h || !U || !std::isfinite(t0)) return RSST_E_ARG;
+  int st = check(rsstk::launch_prime(h->args, U, t0, 1, (hipStream_t)stream));
+  if (st == RSST_OK) h->primed = true;
+  return st;
+}
+
+int rsst_stage(rsst_handle h, void* U, int stage, double dt_fixed, void* stream) {
+  if (!h || !U || !std::isfinite(dt_fixed) || (stage != 1 && stage != 2)) return RSST_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  StageArgs a = h->args;
+  a.dt_fixed = dt_fixed > 0.0 ? dt_fixed : 0.0;
+  if (stage == 1) {
+    if (dt_fixed <= 0.0 && !h->primed) {
+      // CFL dt of U at the current device time
+      if (rsstk::launch_prime(h->args, U, 0.0, 0, s) != hipSuccess) return RSST_E_DEVICE;
+      h->primed = true;
+    }
+    a.uin = U;
+    a.un = nullptr;
+    a.uout = h->u1;
+  } else {
+    a.uin = h->u1;
+    a.un = U;
+    a.uout = U;
+  }
+  if (rsstk::launch_stage(a, stage, s) != hipSuccess) return RSST_E_DEVICE;
+  // a fixed step leaves the device dt at dt_fixed: re-prime before a CFL step
+  if (stage == 2 && dt_fixed > 0.0) h->primed = false;
+  return RSST_OK;
+}
+
+int rsst_step(rsst_handle h, void* U, double dt_fixed, void* stream) {
+  int st = rsst_stage(h, U, 1, dt_fixed, stream);
+  if (st != RSST_OK) return st;
+  return rsst_stage(h, U, 2, dt_fixed, stream);
+}
+
+int rsst_steps(rsst_handle h, void* U, int nsteps, double dt_fixed, void* stream) {
+  if (nsteps < 0) return RSST_E_ARG;
+  for (int q = 0; q < nsteps; ++q) {
+    int st = rsst_step(h, U, dt_fixed, stream);
+    if (st != RSST_OK) return st;
+  }
+  return RSST_OK;
+}
+
+int rsst_get_time(rsst_handle h, double* t, double* dt_next, void* stream) {
+  if (!h) return RSST_E_ARG;
+  double v[2];
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return RSST_E_DEVICE;
+  if (hipMemcpy(v, h->scal, 2 * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+    return RSST_E_DEVICE;
+  if (dt_next) *dt_next = v[rsstk::kDtCur];
+  if (t) *t = v[rsstk::kTime];
+  return RSST_OK;
+}
+
+int rsst_diag(rsst_handle h, const void* U, double out[8], void* stream) {
+  if (!h || !U || !out) return RSST_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  if (rsstk::launch_diag(h->args, U, h->part, h->npart, h->diag_out, s) != hipSuccess)
+    return RSST_E_DEVICE;
+  if (hipMemcpyAsync(out, h->diag_out, 8 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return RSST_E_DEVICE;
+  return check(hipStreamSynchronize(s));
+}
+
+int rsst_poll(rsst_handle h, uint32_t* flags) {
+  if (!h) return RSST_E_ARG;
+  if (hipDeviceSynchronize() != hipSuccess) return RSST_E_DEVICE;
+  uint32_t f = 0;
+  if (hipMemcpy(&f, h->scal + rsstk::kFlags, sizeof(uint32_t), hipMemcpyDeviceToHost) != hipSuccess)
+    return RSST_E_DEVICE;
+  if (f) {
+    uint32_t z = 0;
+    if (hipMemcpy(h->scal + rsstk::kFlags, &z, sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess)
+      return RSST_E_DEVICE;
+  }
+  if (flags) *flags = f;
+  return f ? RSST_E_NONPHYSICAL : RSST_OK;
+}
+
+int rsst_destroy(rsst_handle h) {
+  if (!h) return RSST_E_ARG;
+  (void)hipDeviceSynchronize();
+  (void)hipFree(h->u1);
+  (void)hipFree(h->scal);
+  (void)hipFree(h->part);
+  (void)hipFree(h->diag_out);
+  delete h;
+  return RSST_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,55 @@
+// Internal interface between the C ABI (rsst_api.hip) and the kernels
+// (rsst_kernels.hip).  Not installed; not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rsstk {
+
+// Device-side scalars of one solver, in one small allocation.
+enum Scalar { kDtCur = 0, kTime = 1, kMaxBits = 2, kDone = 3, kFlags = 4, kNumScalars = 8 };
+
+// Launch geometry of the fused stage kernel.
+//   x (axis 0): one lane per cell, a row of nx cells spread over nwx waves;
+//   s (axis 1, 3D only): ts rows stacked in one workgroup, exchanged in LDS;
+//   m (last axis, 2D/3D): marched by each thread in chunks of km planes.
+struct Geometry {
+  int ndim;
+  int nx, ns, nm;   // extents along x, s, m (ns = 1 unless 3D; nm = 1 in 1D)
+  int nwx, ts, km;  // waves per row, rows per tile, planes per chunk
+  int ntile_s, nchunk;
+  int threads;
+  size_t lds_bytes;
+};
+
+struct StageArgs {
+  Geometry geo;
+  long long ncell;
+  int bc_lo[3], bc_hi[3];  // physical axes
+  double inv_dx[3];
+  double gamma, gm1, inv_gm1, inv_xi, f;
+  double g[3];
+  int form;
+  double dt_fixed;   // > 0: use it, else scal[kDtCur]
+  double cfl_h;      // cfl * h, h from the dt rule
+  double t_end;      // > 0: cut dt at t_end
+  double* scal;      // device scalars
+  const void* uin;   // stage input (halo reads)
+  const void* un;    // stage 2: state at the start of the step (pointwise)
+  void* uout;        // stage output
+  const double* bg;  // FP32 perturbation form: background [nv][nbg]
+  int bg_axis;       // -1 uniform
+  int nbg;
+  int prec;          // 0 FP64, 1 FP32 perturbation
+};
+
+Geometry plan_geometry(int ndim, const int n[3]);
+
+hipError_t launch_stage(const StageArgs& a, int stage, hipStream_t s);
+hipError_t launch_prime(const StageArgs& a, const void* u, double t0, int set_t, hipStream_t s);
+hipError_t launch_diag(const StageArgs& a, const void* u, double* partial, int npartial,
+                       double* out8, hipStream_t s);
+int diag_partials(long long ncell);
+
+}  // namespace rsstk

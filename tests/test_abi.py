@@ -1,0 +1,97 @@
+"""The C ABI library: builds, loads without a GPU, exports every symbol that
+include/rsst.h declares, and rejects invalid configurations on the host
+before any device call (no GPU is touched by these tests)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_1812_04135_amd as R
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(rsst_[a-z_0-9]+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    assert os.path.exists(R.LIB_PATH), "run python -m paper_1812_04135_amd.build"
+    out = subprocess.run(["nm", "-D", "--defined-only", R.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (rsst_[a-z_0-9]+)", out))
+    declared = declared_functions()
+    assert declared, "no declarations found"
+    missing = declared - exported
+    assert not missing, missing
+    for name in declared:
+        assert hasattr(R.lib(), name)
+
+
+def test_strerror_and_version():
+    L = R.lib()
+    for code in (0, -1, -2, -3, -4, -5, 7):
+        assert L.rsst_strerror(code)
+    assert "gfx950" in R.rsst_version()
+
+
+def _bad_configs():
+    cfg, _ = W.random_state(2, [16, 12])
+    yield "ndim", dict(cfg, ndim=4)
+    yield "n small", dict(cfg, n=[3, 12, 1])
+    yield "dx", dict(cfg, dx=[0.0, 0.1, 1.0])
+    yield "gamma", dict(cfg, gamma=1.0)
+    yield "xi", dict(cfg, xi=0.5)
+    yield "cfl", dict(cfg, cfl=1.5)
+    yield "form", dict(cfg, form=9)
+    yield "bc mix", dict(cfg, bc_lo=["periodic", "reflect"], bc_hi=["periodic", "periodic"])
+    yield "dt_rule", dict(cfg, dt_rule=3)
+
+
+@pytest.mark.parametrize("name,cfg", list(_bad_configs()))
+def test_invalid_config_rejected_on_host(name, cfg):
+    c = R.make_config(cfg)
+    h = ctypes.c_void_p()
+    code = R.lib().rsst_init(ctypes.byref(c), None, ctypes.byref(h))
+    assert code == -1, name
+    assert not h.value
+
+
+def test_unused_axis_must_be_one():
+    cfg, _ = W.random_state(2, [16, 12])
+    c = R.make_config(cfg)
+    c.n[2] = 2
+    h = ctypes.c_void_p()
+    assert R.lib().rsst_init(ctypes.byref(c), None, ctypes.byref(h)) == -1
+
+
+def test_fp32_perturbation_needs_background():
+    cfg, _ = W.random_state(2, [16, 12])
+    c = R.make_config(cfg, prec="fp32_pert", bg=None)
+    h = ctypes.c_void_p()
+    assert R.lib().rsst_init(ctypes.byref(c), None, ctypes.byref(h)) == -1
+
+
+def test_unsupported_shape_reported():
+    cfg, _ = W.random_state(3, [300, 8, 8])
+    c = R.make_config(cfg)
+    h = ctypes.c_void_p()
+    assert R.lib().rsst_init(ctypes.byref(c), None, ctypes.byref(h)) == -4
+
+
+def test_null_arguments():
+    L = R.lib()
+    assert L.rsst_step(None, None, ctypes.c_double(0.0), None) == -1
+    assert L.rsst_poll(None, None) == -1
+    assert L.rsst_destroy(None) == -1
+    h = ctypes.c_void_p()
+    assert L.rsst_init(None, None, ctypes.byref(h)) == -1

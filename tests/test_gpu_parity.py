@@ -1,0 +1,260 @@
+"""GPU path (through the C ABI) against the CPU oracle, element by element.
+
+Tolerance (FP64): per variable v, max|U_gpu - U_oracle| <= 1e-12 * s_v with
+the natural scales s_rho = max|rho|, s_E = max|E| and s_m = max|rho| * max a
+(momentum at Mach 1).  Two independently ordered FP64 codes (FMA contraction
+on the GPU, none in the oracle) differ by rounding only; measured against a
+momentum perturbation of 1e-4 that rounding random-walks to ~1e-11 over
+hundreds of steps, which is why momentum is scaled by rho*a.
+
+FP32 perturbation form: max|U1_gpu - (U_oracle - U0)| <= 1e-5 * s1 per
+variable, the oracle run in FP64 from U0 + U1(t=0), with s1 = max|U_oracle - U0|
+for rho and E, and for every momentum component the largest perturbation of
+any component (momentum is one vector: FP32 rounding of its largest component
+feeds absolute errors of that size into all of them).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+R = None
+
+
+def setup_module(module):
+    global R
+    import paper_1812_04135_amd as lib
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    lib.lib()  # must load the HIP library, no fallback
+    R = lib
+
+
+GAMMA = 5.0 / 3.0
+
+
+def scales(U, ndim):
+    rho = U[0]
+    m2 = sum(U[1 + d] ** 2 for d in range(ndim))
+    P = (GAMMA - 1) * (U[-1] - 0.5 * m2 / rho)
+    a = np.sqrt(GAMMA * np.abs(P) / rho)
+    srho = np.abs(rho).max()
+    return [srho] + [srho * a.max()] * ndim + [np.abs(U[-1]).max()]
+
+
+def parity_err(Ug, Uo, ndim):
+    s = scales(Uo, ndim)
+    return [float(np.abs(Ug[v] - Uo[v]).max() / s[v]) for v in range(ndim + 2)]
+
+
+def assert_parity(Ug, Uo, ndim, tol=1e-12, what=""):
+    err = parity_err(Ug, Uo, ndim)
+    print(f"[parity] {what} err/scale per var = {['%.2e' % e for e in err]}", flush=True)
+    assert max(err) <= tol, (what, err)
+
+
+def pert_errors(Ug, Uo, bg, ndim):
+    pert = Uo - bg
+    s = [np.abs(pert[v]).max() for v in range(ndim + 2)]
+    sm = max(s[1:1 + ndim])
+    s = [s[0]] + [sm] * ndim + [s[-1]]
+    return [float(np.abs(Ug[v].astype(np.float64) - pert[v]).max() / s[v])
+            for v in range(ndim + 2)]
+
+
+def gpu_run(cfg, U0, nsteps, dt_fixed=0.0, t_end=0.0, prec="fp64", bg=None, bg_axis=-1):
+    U = torch.from_numpy(np.ascontiguousarray(U0)).cuda()
+    bgt = torch.from_numpy(bg).cuda() if bg is not None else None
+    sol = R.Solver(cfg, prec=prec, bg=bgt, bg_axis=bg_axis, t_end=t_end)
+    sol.steps(U, nsteps, dt_fixed)
+    torch.cuda.synchronize()
+    t, dt = sol.time()
+    flags = sol.poll()
+    out = U.cpu().numpy()
+    sol.close()
+    return out, t, dt, flags
+
+
+CASES = [
+    # (ndim, n, bc_lo, g, form)
+    (1, [37], ["periodic"], None, "pvs"),
+    (1, [130], ["reflect"], [-0.3], "pms"),
+    (1, [256], ["periodic"], None, "dvs"),
+    (1, [64], ["reflect"], [0.5], "dms"),
+    (1, [100], ["periodic"], None, "pd"),
+    (1, [50], ["reflect"], None, "euler"),
+    (2, [70, 45], ["periodic", "periodic"], None, "pvs"),
+    (2, [37, 20], ["periodic", "reflect"], [0.0, -0.5], "pms"),
+    (2, [64, 16], ["reflect", "periodic"], [0.2, 0.0], "dvs"),
+    (2, [130, 12], ["reflect", "reflect"], [0.1, -0.4], "dms"),
+    (2, [20, 33], ["periodic", "reflect"], [0.0, -1.0], "pd"),
+    (2, [200, 8], ["periodic", "periodic"], None, "euler"),
+    (3, [37, 13, 11], ["periodic"] * 3, None, "pvs"),
+    (3, [20, 9, 10], ["periodic", "periodic", "reflect"], [0.0, 0.0, -1.0], "pvs"),
+    (3, [130, 9, 6], ["reflect", "reflect", "periodic"], [0.3, -0.2, 0.0], "pms"),
+    (3, [64, 8, 8], ["periodic", "reflect", "reflect"], [0.0, 0.4, -0.6], "dvs"),
+    (3, [17, 6, 5], ["reflect", "periodic", "periodic"], None, "dms"),
+    (3, [256, 4, 4], ["periodic"] * 3, [0.0, 0.0, -0.5], "pd"),
+    (3, [40, 10, 7], ["reflect"] * 3, None, "euler"),
+]
+
+
+@pytest.mark.parametrize("ndim,n,bc,g,form", CASES,
+                         ids=[f"{c[0]}d-{'x'.join(map(str, c[1]))}-{c[4]}-{c[2][0][0]}{c[2][-1][0]}"
+                              for c in CASES])
+def test_step_matches_oracle(ndim, n, bc, g, form):
+    cfg, U0 = W.random_state(ndim, n, seed_k=200 + sum(n), xi=4.0, form=form, bc_lo=bc,
+                             g=g, mach=0.3)
+    nsteps = 6
+    print(f"[case] {ndim}D n={n} bc={bc} form={form}", flush=True)
+    Ug, tg, dtg, flags = gpu_run(cfg, U0, nsteps)
+    Uo, to, dto = oracle.run(cfg, U0, nsteps)
+    assert flags == 0
+    assert abs(tg - to) <= 1e-13 * to
+    assert_parity(Ug, Uo, ndim, what=f"{ndim}D {n} {form}")
+
+
+@pytest.mark.parametrize("form", ["pvs", "pms", "dvs", "dms", "pd", "euler"])
+def test_fixed_dt_and_xi_one(form):
+    cfg, U0 = W.random_state(2, [48, 40], seed_k=300, xi=1.0 if form == "euler" else 7.0,
+                             form=form, bc_lo=["periodic", "reflect"], g=[0.0, -0.7])
+    Ug, tg, _, _ = gpu_run(cfg, U0, 5, dt_fixed=1e-3)
+    Uo, to, _ = oracle.run(cfg, U0, 5, dt_fixed=1e-3)
+    assert abs(tg - 5e-3) < 1e-15
+    assert_parity(Ug, Uo, 2, what=f"fixed dt {form}")
+
+
+def test_t_end_truncates_last_step():
+    cfg, U0, meta = W.wave1d(xi=10.0, form="pvs")
+    t_end = 0.05 * meta["t_end"]
+    Ug, tg, _, _ = gpu_run(cfg, U0, 1000, t_end=t_end)
+    Uo, to, _ = oracle.run(cfg, U0, 1000, t_end=t_end)
+    assert tg == pytest.approx(t_end, rel=1e-14) and to == pytest.approx(t_end, rel=1e-14)
+    assert_parity(Ug, Uo, 1, what="t_end")
+
+
+def test_linear_wave_full_length():
+    """1D periodic wave, 256 cells, xi = 10, to t = 2 reduced crossing times."""
+    for xi in (1.0, 10.0):
+        cfg, U0, meta = W.wave1d(xi=xi, form="pvs")
+        Ug, tg, _, _ = gpu_run(cfg, U0, 100000, t_end=meta["t_end"])
+        Uo, to, _ = oracle.run(cfg, U0, 100000, t_end=meta["t_end"])
+        assert tg == pytest.approx(meta["t_end"], rel=1e-13)
+        assert_parity(Ug, Uo, 1, what=f"wave1d xi={xi}")
+
+
+def test_bubble2d_full_size_20_steps():
+    cfg, U0, meta = W.bubble2d()
+    Ug, tg, _, _ = gpu_run(cfg, U0, 20)
+    Uo, to, _ = oracle.run(cfg, U0, 20)
+    assert abs(tg - to) <= 1e-13 * to
+    assert_parity(Ug, Uo, 2, what="bubble2d 512^2 x20")
+
+
+def test_strat3d_full_size_one_step_from_evolved_state():
+    """256^3 stratified box: evolve 5 steps on the GPU, then compare one more
+    GPU step with one oracle step from the same state."""
+    cfg, U0, meta = W.strat3d()
+    U = torch.from_numpy(U0).cuda()
+    sol = R.Solver(cfg)
+    sol.steps(U, 5)
+    torch.cuda.synchronize()
+    Us = U.cpu().numpy()
+    sol.step(U)
+    torch.cuda.synchronize()
+    t5 = sol.time()[0]
+    Ug = U.cpu().numpy()
+    sol.close()
+    Uo, _, dto = oracle.run(cfg, Us, 1)
+    assert_parity(Ug, Uo, 3, what="strat3d 256^3 one step")
+
+
+def test_fp32_perturbation_matches_fp64_oracle_3d():
+    cfg, U0, meta = W.strat3d(n=32, nz=24, ny=16, xi=30.0)
+    bg = meta["bg"]
+    U1 = (U0 - bg[:, :, None, None]).astype(np.float32)
+    Ustart = bg[:, :, None, None] + U1.astype(np.float64)
+    nsteps = 20
+    Ug, tg, _, flags = gpu_run(cfg, U1, nsteps, prec="fp32_pert", bg=bg, bg_axis=2)
+    Uo, to, _ = oracle.run(cfg, Ustart, nsteps)
+    assert flags == 0
+    assert abs(tg - to) <= 1e-6 * to
+    err = pert_errors(Ug, Uo, bg[:, :, None, None], 3)
+    print(f"[fp32 3d] err/|pert| per var = {['%.2e' % e for e in err]}", flush=True)
+    assert max(err) <= 1e-5, err
+
+
+def test_fp32_perturbation_matches_fp64_oracle_2d_uniform_bg():
+    cfg, U0, meta = W.bubble2d(n=96, xi=20.0)
+    bg = meta["bg"]
+    U1 = (U0 - bg[:, :, None]).astype(np.float32)
+    Ustart = bg[:, :, None] + U1.astype(np.float64)
+    Ug, tg, _, _ = gpu_run(cfg, U1, 20, prec="fp32_pert", bg=bg, bg_axis=-1)
+    Uo, to, _ = oracle.run(cfg, Ustart, 20)
+    err = pert_errors(Ug, Uo, bg[:, :, None], 2)
+    print(f"[fp32 2d] err/|pert| per var = {['%.2e' % e for e in err]}", flush=True)
+    assert max(err) <= 1e-5, err
+
+
+# ------------------------------------------------------------ invariants
+
+def test_uniform_state_bitwise_3d():
+    n = [40, 9, 11]
+    cfg = W.base_cfg(3, n, xi=5.0, form="pvs")
+    shape = tuple(reversed(n))
+    U0 = W.conservative(np.full(shape, 1.2), [np.full(shape, 0.1), np.full(shape, -0.05),
+                                               np.full(shape, 0.02)], np.full(shape, 0.8))
+    Ug, _, _, _ = gpu_run(cfg, U0, 10)
+    assert np.array_equal(Ug, U0)
+
+
+def test_translation_invariance_bitwise():
+    """A periodic shift that is not a multiple of any tile or wave moves the
+    result bit for bit (tile seams and halos compute the same numbers)."""
+    cfg, U0 = W.random_state(3, [100, 14, 12], seed_k=400, xi=3.0)
+    Ua, _, _, _ = gpu_run(cfg, U0, 3)
+    Us = np.ascontiguousarray(np.roll(U0, shift=(5, 3, 37), axis=(1, 2, 3)))
+    Ub, _, _, _ = gpu_run(cfg, Us, 3)
+    assert np.array_equal(np.roll(Ua, shift=(5, 3, 37), axis=(1, 2, 3)), Ub)
+
+
+@pytest.mark.parametrize("form", ["dvs", "pd", "euler"])
+def test_mass_conservation_on_gpu(form):
+    cfg, U0 = W.random_state(2, [96, 64], seed_k=401, xi=4.0 if form != "euler" else 1.0,
+                             form=form)
+    U = torch.from_numpy(U0).cuda()
+    sol = R.Solver(cfg)
+    m0 = sol.diag(U)[0]
+    sol.steps(U, 50)
+    m1 = sol.diag(U)[0]
+    sol.close()
+    assert abs(m1 - m0) <= 1e-13 * abs(m0)
+
+
+def test_diag_matches_oracle():
+    cfg, U0 = W.random_state(3, [40, 12, 10], seed_k=402, xi=6.0)
+    U = torch.from_numpy(U0).cuda()
+    sol = R.Solver(cfg)
+    d = sol.diag(U)
+    sol.close()
+    do = oracle.diag(cfg, U0)
+    np.testing.assert_allclose(d, do, rtol=1e-13, atol=1e-15)
+
+
+def test_nonphysical_state_is_latched_and_polled():
+    cfg, U0 = W.random_state(2, [32, 16], seed_k=403)
+    U0 = U0.copy()
+    U0[0, 5, 7] = float("nan")
+    U = torch.from_numpy(U0).cuda()
+    sol = R.Solver(cfg)
+    sol.step(U, dt_fixed=1e-4)
+    with pytest.raises(R.RsstError) as e:
+        sol.poll()
+    assert e.value.code == -5
+    assert sol.poll() == 0  # cleared
+    sol.close()
