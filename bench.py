@@ -54,6 +54,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="only run a plain device copy of one 256^3 FP64 state (5 x 134 MB), "
+                         "the reference kernel for scaling HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build measures one GPU only (the step is single-device; "
@@ -68,6 +71,14 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_ref:
+        x = torch.ones(5 * 256 ** 3, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_ref_bytes_read": x.numel() * 8, "copy_ref_bytes_written": x.numel() * 8}))
+        return
     cfg, U0, meta = W.strat3d(n=256, xi=30.0, form="pvs")
     nv, ncell = U0.shape[0], U0[0].size
     U = torch.from_numpy(U0).to(dev)

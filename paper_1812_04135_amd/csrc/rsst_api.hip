@@ -60,6 +60,12 @@ static int validate(const rsst_config* c) {
     if (c->bg_axis < -1 || c->bg_axis >= c->ndim) return RSST_E_ARG;
   }
   if (!(c->t_end >= 0.0) || !std::isfinite(c->t_end)) return RSST_E_ARG;
+  // fields are addressed with 32-bit byte offsets
+  {
+    const long long cells = (long long)c->n[0] * c->n[1] * c->n[2];
+    const long long bytes = cells * (c->ndim + 2) * (c->prec == RSST_FP32_PERT ? 4 : 8);
+    if (bytes >= (1ll << 31)) return RSST_E_UNSUPPORTED;
+  }
   // supported launch shapes: whole x rows in one workgroup
   if (c->ndim == 1 && c->n[0] > 1024) return RSST_E_UNSUPPORTED;
   if (c->ndim == 2 && c->n[0] > 1024) return RSST_E_UNSUPPORTED;

@@ -39,56 +39,83 @@ struct Face {
   double vn;
 };
 
-// Monotonized-central limited slope.  On the l*r > 0 branch l and r share a
-// sign, so |l + r| = |l| + |r| exactly and sign(l + r) = sign(l): the value
-// equals sign(l+r) min(|l+r|/2, 2|l|, 2|r|) bit for bit (Sec. 4.1, item 2).
-__device__ __forceinline__ double mc_slope(double l, double r) {
-  const double al = fabs(l), ar = fabs(r);
-  const double q = fmin(0.5 * (al + ar), 2.0 * fmin(al, ar));
-  return (l * r > 0.0) ? copysign(q, l) : 0.0;
+// Reciprocal: hardware seed refined by two Newton steps (about 1 ulp).
+__device__ __forceinline__ double rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
 }
 
-// Primitive recovery of a face state, normal axis D (Sec. 3.2 and 4.1).
+// Square root of x >= 0: reciprocal-square-root seed and one coupled Newton
+// step on (s, h) = (x y, y/2); sqrt(0) = 0.
+__device__ __forceinline__ double sqrt_nr(double x) {
+  const double y = __builtin_amdgcn_rsq(fmax(x, 1e-300));
+  const double s = x * y, h = 0.5 * y;
+  return fma(fma(-s, s, x), h, s);
+}
+
+// Half of the monotonized-central limited slope (Sec. 4.1, item 2):
+//   MC(l, r) = 0 if l r <= 0, else sign(l+r) min(|l+r|/2, 2|l|, 2|r|).
+// With s = sign(l) this is s max(0, min(2|l|, s(l+r)/2, 2 s r)); the
+// function returns MC/2 = s max(0, min(|l|, s r, (|l| + s r)/4)), which is
+// the offset of the face states from the cell value.  On the l r > 0 branch
+// |l| + |r| = |l + r| exactly, so the result equals MC/2 bit for bit.
+__device__ __forceinline__ double mc_half(double l, double r) {
+  const int sgn = __double2hiint(l) & 0x80000000;
+  const double sr = __hiloint2double(__double2hiint(r) ^ sgn, __double2loint(r));
+  const double al = fabs(l);
+  const double h = fmax(fmin(fmin(al, sr), 0.25 * (al + sr)), 0.0);
+  return __hiloint2double(__double2hiint(h) | sgn, __double2loint(h));
+}
+
+// Primitive recovery of a face state, normal axis D (Sec. 3.2 and 4.1):
+// V = m/rho, P = (gamma-1)(E - rho|V|^2/2), c_tot = |V| + sqrt(gamma P/rho)/xi.
 template <int NDIM, int D>
 __device__ __forceinline__ void face_prims(Face<NDIM + 2>& s, const Consts& K) {
   constexpr int NV = NDIM + 2;
-  const double rinv = 1.0 / s.u[0];
-  double v2 = 0.0, mv = 0.0, vn = 0.0;
+  const double ri = rcp(s.u[0]);
+  double v2 = 0.0, vn = 0.0;
 #pragma unroll
   for (int e = 0; e < NDIM; ++e) {
-    const double ve = s.u[1 + e] * rinv;
+    const double ve = s.u[1 + e] * ri;
     v2 = fma(ve, ve, v2);
-    mv = fma(s.u[1 + e], ve, mv);
     if (e == D) vn = ve;
   }
-  s.P = K.gm1 * fma(-0.5, mv, s.u[NV - 1]);
-  const double a2 = K.gamma * s.P * rinv;
-  s.c = fma(sqrt(a2), K.inv_xi, sqrt(v2));
+  s.P = K.gm1 * fma(-0.5 * s.u[0], v2, s.u[NV - 1]);
+  s.c = fma(sqrt_nr(K.gamma * s.P * ri), K.inv_xi, sqrt_nr(v2));
   s.vn = vn;
 }
 
-// Euler flux of a face state along its normal axis D (eq. pvs_dt0).
+// Face state U + h (h: half slopes, signed) and its primitives.
 template <int NDIM, int D>
-__device__ __forceinline__ void face_flux(const Face<NDIM + 2>& s, double (&F)[NDIM + 2]) {
-  constexpr int NV = NDIM + 2;
-  F[0] = s.u[1 + D];
+__device__ __forceinline__ void make_face(const double (&u)[NDIM + 2], const double (&h)[NDIM + 2],
+                                          bool plus, const Consts& K, Face<NDIM + 2>& s) {
 #pragma unroll
-  for (int e = 0; e < NDIM; ++e) F[1 + e] = (e == D) ? fma(s.u[1 + e], s.vn, s.P) : s.u[1 + e] * s.vn;
-  F[NV - 1] = (s.u[NV - 1] + s.P) * s.vn;
+  for (int v = 0; v < NDIM + 2; ++v) s.u[v] = plus ? u[v] + h[v] : u[v] - h[v];
+  face_prims<NDIM, D>(s, K);
 }
 
-// Local Lax-Friedrichs flux between left state L and right state R along D:
-// Fhat = (F(L) + F(R))/2 - max(c_L, c_R) (U_R - U_L)/2   (Sec. 4.1, item 4).
+// Twice the local Lax-Friedrichs flux between left state L and right state
+// R along D (Sec. 4.1, item 4):
+//   G = F(U_L) + F(U_R) - max(c_L, c_R) (U_R - U_L) = 2 Fhat,
+// with the Euler flux F_d(U) = (m_d, m_e V_d + P delta_de, (E + P) V_d).
+// The factor 1/2 is folded into the 1/dx of the divergence.
 template <int NDIM, int D>
-__device__ __forceinline__ void llf(const Face<NDIM + 2>& L, const Face<NDIM + 2>& R,
-                                    double (&F)[NDIM + 2]) {
+__device__ __forceinline__ void flux2(const Face<NDIM + 2>& L, const Face<NDIM + 2>& R,
+                                      double (&G)[NDIM + 2]) {
   constexpr int NV = NDIM + 2;
-  double FL[NV], FR[NV];
-  face_flux<NDIM, D>(L, FL);
-  face_flux<NDIM, D>(R, FR);
-  const double ha = 0.5 * fmax(L.c, R.c);
+  const double a = fmax(L.c, R.c);
+  G[0] = fma(-a, R.u[0] - L.u[0], L.u[1 + D] + R.u[1 + D]);
 #pragma unroll
-  for (int v = 0; v < NV; ++v) F[v] = fma(-ha, R.u[v] - L.u[v], 0.5 * (FL[v] + FR[v]));
+  for (int e = 0; e < NDIM; ++e) {
+    const double fl = (e == D) ? fma(L.u[1 + e], L.vn, L.P) : L.u[1 + e] * L.vn;
+    const double fr = (e == D) ? fma(R.u[1 + e], R.vn, R.P) : R.u[1 + e] * R.vn;
+    G[1 + e] = fma(-a, R.u[1 + e] - L.u[1 + e], fl + fr);
+  }
+  const double el = (L.u[NV - 1] + L.P) * L.vn, er = (R.u[NV - 1] + R.P) * R.vn;
+  G[NV - 1] = fma(-a, R.u[NV - 1] - L.u[NV - 1], el + er);
 }
 
 // Mirror image of a face state across a wall normal to D.
@@ -100,80 +127,60 @@ __device__ __forceinline__ Face<NDIM + 2> mirror(const Face<NDIM + 2>& s) {
   return m;
 }
 
-// Build a face state U0 +- sigma/2 and its primitives.
-template <int NDIM, int D>
-__device__ __forceinline__ void make_face(const double (&u)[NDIM + 2], const double (&sig)[NDIM + 2],
-                                          double sgn, const Consts& K, Face<NDIM + 2>& s) {
-#pragma unroll
-  for (int v = 0; v < NDIM + 2; ++v) s.u[v] = fma(0.5 * sgn, sig[v], u[v]);
-  face_prims<NDIM, D>(s, K);
-}
-
 // Corrected time derivative of one cell (eq. pvs_dt, pvs_dt_dpr; App. A.1-A.4)
 // plus the external force (App. B).  u: stage-input cell state; Dl: the
 // uncorrected increments (Delta rho, Delta m_i, Delta E).  Returns the
 // non-physical flags of the cell.
-template <int NDIM>
+template <int NDIM, int FORM>
 __device__ __forceinline__ unsigned rsst_rate(const double (&u)[NDIM + 2], const double (&Dl)[NDIM + 2],
-                                              const Consts& K, int form, const double (&g)[3],
+                                              const Consts& K, const double (&g)[3],
                                               double (&R)[NDIM + 2]) {
   constexpr int NV = NDIM + 2;
   const double rho = u[0];
-  const double rinv = 1.0 / rho;
+  const double ri = rcp(rho);
   double v[NDIM];
-  double v2 = 0.0, mv = 0.0, vdm = 0.0;
+  double v2 = 0.0, vdm = 0.0;
 #pragma unroll
   for (int e = 0; e < NDIM; ++e) {
-    v[e] = u[1 + e] * rinv;
+    v[e] = u[1 + e] * ri;
     v2 = fma(v[e], v[e], v2);
-    mv = fma(u[1 + e], v[e], mv);
     vdm = fma(v[e], Dl[1 + e], vdm);
   }
-  const double P = K.gm1 * fma(-0.5, mv, u[NV - 1]);
+  const double P = K.gm1 * fma(-0.5 * rho, v2, u[NV - 1]);
   unsigned bad = 0;
   if (!(rho > 0.0)) bad |= kBadRho;
   if (!(P > 0.0)) bad |= kBadP;
   if (!(fabs(u[NV - 1]) < INFINITY) || !(fabs(P) < INFINITY)) bad |= kNonFinite;
-  // Delta P = (gamma-1) (|V|^2/2 Delta rho - V.Delta m + Delta E)
-  const double dP = K.gm1 * (fma(0.5 * v2, Dl[0], Dl[NV - 1]) - vdm);
-  const double H = (u[NV - 1] + P) * rinv;  // (E + P)/rho
 #pragma unroll
   for (int q = 0; q < NV; ++q) R[q] = Dl[q];
-  switch (form) {
-    case kPVS: {  // coefficients (1, V, H)/a^2 on Delta P
-      const double s = K.f * dP * rho / (K.gamma * P);
+  if constexpr (FORM != kEuler) {
+    // Delta P = (gamma-1) (|V|^2/2 Delta rho - V.Delta m + Delta E)
+    const double dP = K.gm1 * (fma(0.5 * v2, Dl[0], Dl[NV - 1]) - vdm);
+    const double H = (u[NV - 1] + P) * ri;  // (E + P)/rho
+    if constexpr (FORM == kPVS || FORM == kPMS) {
+      // s = f Delta P / a^2, a^2 = gamma P / rho
+      const double s = K.f * dP * rho * rcp(K.gamma * P);
       R[0] -= s;
+      if constexpr (FORM == kPVS) {
 #pragma unroll
-      for (int e = 0; e < NDIM; ++e) R[1 + e] = fma(-v[e], s, R[1 + e]);
-      R[NV - 1] = fma(-H, s, R[NV - 1]);
-      break;
-    }
-    case kPMS: {  // (1, 0, H - |V|^2)/a^2 on Delta P; momentum conservative
-      const double s = K.f * dP * rho / (K.gamma * P);
-      R[0] -= s;
-      R[NV - 1] = fma(-(H - v2), s, R[NV - 1]);
-      break;
-    }
-    case kDVS: {  // (1, V, H) on Delta rho
+        for (int e = 0; e < NDIM; ++e) R[1 + e] = fma(-v[e], s, R[1 + e]);
+        R[NV - 1] = fma(-H, s, R[NV - 1]);
+      } else {
+        R[NV - 1] = fma(-(H - v2), s, R[NV - 1]);
+      }
+    } else if constexpr (FORM == kDVS || FORM == kDMS) {
       const double s = K.f * Dl[0];
       R[0] -= s;
+      if constexpr (FORM == kDVS) {
 #pragma unroll
-      for (int e = 0; e < NDIM; ++e) R[1 + e] = fma(-v[e], s, R[1 + e]);
-      R[NV - 1] = fma(-H, s, R[NV - 1]);
-      break;
-    }
-    case kDMS: {  // (1, 0, H - |V|^2) on Delta rho
-      const double s = K.f * Dl[0];
-      R[0] -= s;
-      R[NV - 1] = fma(-(H - v2), s, R[NV - 1]);
-      break;
-    }
-    case kPD: {  // energy only: (de/dP)_rho Delta P
+        for (int e = 0; e < NDIM; ++e) R[1 + e] = fma(-v[e], s, R[1 + e]);
+        R[NV - 1] = fma(-H, s, R[NV - 1]);
+      } else {
+        R[NV - 1] = fma(-(H - v2), s, R[NV - 1]);
+      }
+    } else {  // PD: energy only, (de/dP)_rho Delta P
       R[NV - 1] = fma(-K.f * K.inv_gm1, dP, R[NV - 1]);
-      break;
     }
-    default:
-      break;
   }
 #pragma unroll
   for (int e = 0; e < NDIM; ++e) {
@@ -187,16 +194,15 @@ __device__ __forceinline__ unsigned rsst_rate(const double (&u)[NDIM + 2], const
 template <int NDIM>
 __device__ __forceinline__ double cell_ctot(const double (&u)[NDIM + 2], const Consts& K) {
   constexpr int NV = NDIM + 2;
-  const double rinv = 1.0 / u[0];
-  double v2 = 0.0, mv = 0.0;
+  const double ri = rcp(u[0]);
+  double v2 = 0.0;
 #pragma unroll
   for (int e = 0; e < NDIM; ++e) {
-    const double ve = u[1 + e] * rinv;
+    const double ve = u[1 + e] * ri;
     v2 = fma(ve, ve, v2);
-    mv = fma(u[1 + e], ve, mv);
   }
-  const double P = K.gm1 * fma(-0.5, mv, u[NV - 1]);
-  return fma(sqrt(K.gamma * P * rinv), K.inv_xi, sqrt(v2));
+  const double P = K.gm1 * fma(-0.5 * u[0], v2, u[NV - 1]);
+  return fma(sqrt_nr(K.gamma * P * ri), K.inv_xi, sqrt_nr(v2));
 }
 
 // ---- cross-lane moves (wave64 DPP) -------------------------------------
