@@ -151,6 +151,59 @@ def main():
         "library": version,
     }
 
+    # ---- secondary workloads (same GPU, same library), each with its error
+    sec = {}
+
+    def timed(sol, U, nsteps, warm=3):
+        for _ in range(warm):
+            sol.step(U)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(nsteps):
+            sol.step(U)
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / nsteps
+
+    # FP32 perturbation about the FP64 polytrope, same 256^3 box
+    bg = torch.from_numpy(meta["bg"]).to(dev)
+    U1_0 = (U0 - meta["bg"][:, :, None, None]).astype(np.float32)
+    U32 = torch.from_numpy(U1_0).to(dev)
+    s32 = R.Solver(cfg, prec="fp32_pert", bg=bg, bg_axis=2)
+    ms32 = timed(s32, U32, K)
+    s32.close()
+    sec["strat3d_fp32_pert"] = {
+        "ms_per_step": round(ms32, 5), "Gcell_updates_s": round(ncell / (ms32 * 1e-3) / 1e9, 4),
+        "effective_GBs": round(5 * nv * 4 * ncell / (ms32 * 1e-3) / 1e9, 1),
+        "speedup_vs_fp64": round(ms_step / ms32, 3)}
+
+    # 2D bubble 512^2 FP64 (L2/MALL resident; launch-latency sensitive)
+    cfg2, U2_0, _ = W.bubble2d()
+    U2 = torch.from_numpy(U2_0).to(dev)
+    s2 = R.Solver(cfg2)
+    ms2 = timed(s2, U2, 200)
+    s2.close()
+    n2 = U2_0[0].size
+    sec["bubble2d_512_fp64"] = {"ms_per_step": round(ms2, 5),
+                                "Gcell_updates_s": round(n2 / (ms2 * 1e-3) / 1e9, 4)}
+
+    # 1D wave, 256 cells, xi = 10, the whole run to t_end (2 reduced crossings)
+    cfg1, U1w, meta1 = W.wave1d(xi=10.0)
+    Uw = torch.from_numpy(U1w).to(dev)
+    s1 = R.Solver(cfg1, t_end=meta1["t_end"])
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    s1.steps(Uw, 1300)
+    b.record(stream)
+    torch.cuda.synchronize()
+    t1, _ = s1.time()
+    s1.close()
+    sec["wave1d_256_xi10"] = {"steps": 1300, "t_reached": t1, "t_end": meta1["t_end"],
+                              "steps_per_s": round(1300 / (a.elapsed_time(b) * 1e-3), 1)}
+    out["secondary"] = sec
+
     if not args.no_cpu:
         import oracle
         # the CPU oracle on a bounded sample: cpu_steps full 256^3 steps from
@@ -164,6 +217,22 @@ def main():
         torch.cuda.synchronize()
         err = parity_err(Ug.cpu().numpy(), Uo, 3)
         s.close()
+        # FP32 perturbation on the same sample, against the same FP64 oracle
+        # run from U0 + fp32(U - U0)
+        Ustart = meta["bg"][:, :, None, None] + U1_0.astype(np.float64)
+        Uo32, _, _ = oracle.run(cfg, Ustart, args.cpu_steps)
+        Ug32 = torch.from_numpy(U1_0).to(dev)
+        s = R.Solver(cfg, prec="fp32_pert", bg=bg, bg_axis=2)
+        s.steps(Ug32, args.cpu_steps)
+        torch.cuda.synchronize()
+        pert = Uo32 - meta["bg"][:, :, None, None]
+        g32 = Ug32.cpu().numpy().astype(np.float64)
+        sc = [np.abs(pert[v]).max() for v in range(nv)]
+        sm = max(sc[1:4])
+        sc = [sc[0], sm, sm, sm, sc[4]]
+        err32 = max(float(np.abs(g32[v] - pert[v]).max() / sc[v]) for v in range(nv))
+        s.close()
+        out["secondary"]["strat3d_fp32_pert"]["err_vs_oracle_pert"] = err32
         out["cpu_baseline"] = {"value": round(ncell * args.cpu_steps / cpu_s / 1e9, 6),
                                "unit": "Gcell-updates/s", "cores": oracle.threads(),
                                "kind": "oracle",

@@ -716,9 +716,15 @@ Geometry plan_geometry(int ndim, const int n[3]) {
   if (ndim == 1) {
     G.km = 1;
   } else {
-    // enough workgroups to fill 256 CUs, chunks no shorter than 8 planes
-    int km = 32;
-    while (km > 8 && (long long)G.ntile_s * ((G.nm + km - 1) / km) < 1024) km >>= 1;
+    // at least two workgroups per CU (256 CUs), chunks of 8 to 64 planes
+    // (each chunk re-reads 4 planes to start its march); RSST_KM overrides
+    // the chunk length (tuning)
+    int km = 64;
+    while (km > 8 && (long long)G.ntile_s * ((G.nm + km - 1) / km) < 512) km >>= 1;
+    if (const char* e = getenv("RSST_KM")) {
+      const int v = atoi(e);
+      if (v >= 4 && v <= 4096) km = v;
+    }
     G.km = km < G.nm ? km : G.nm;
   }
   G.nchunk = (G.nm + G.km - 1) / G.km;
