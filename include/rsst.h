@@ -130,6 +130,58 @@ int rsst_poll(rsst_handle h, uint32_t* flags);
 /* Frees the workspace.  The caller's arrays are untouched. */
 int rsst_destroy(rsst_handle h);
 
+/* ---- Batched boxes ------------------------------------------------------
+ * Many independent 2D boxes (each with its own size, xi, gravity, boundaries
+ * and background) advanced together by one persistent kernel per run; the
+ * run (counter reset, per-box CFL prime, persistent kernel) is captured in a
+ * HIP graph on first use and replayed while U_all, nsteps and the strip rows
+ * are unchanged.  Each box takes its own CFL dt every step, from the
+ * maximum c_tot over that box only.  Same numerics as rsst_step per box.
+ * This build: ndim = 2, n[0] <= 256, one form and one prec for all boxes,
+ * t_end = 0; FP32_PERT backgrounds vary along y (bg_axis = 1) or not (-1). */
+typedef struct rsst_batch_s* rsst_batch;
+
+/* boxes[nbox]: per-box configurations (validated on the host).  offsets[b]:
+ * element offset of box b's [nvar][ny][nx] block inside the caller's U_all
+ * array (FP64, or FP32 for FP32_PERT); blocks must not overlap.  max_steps:
+ * the largest nsteps a run will ask for (sizes the per-step counters).
+ * Allocates the stage buffer and the queue state; nothing after this call
+ * except the graph of a run. */
+int rsst_batch_init(const rsst_config* boxes, int nbox, const int64_t* offsets, int max_steps,
+                    void* stream, rsst_batch* out);
+
+/* Rows per strip of the march for boxes whose rows span 1, 2, 3 and 4 waves
+ * (nx in 1..64, 65..128, 129..192, 193..256); each in [8, 256].  Takes
+ * effect at the next run (re-captures the graph).  Default 16. */
+int rsst_batch_set_tiles(rsst_batch h, const int strip_rows[4]);
+int rsst_batch_get_tiles(rsst_batch h, int strip_rows[4]);
+
+/* The work items a run would execute for these boxes and strip rows, on the
+ * host only (no device call): one row of RSST_BATCH_PLAN_COLS ints per
+ * item, (box, block, first row, end row, ndep, dep[0..7]) where dep lists
+ * the blocks of the same box (-1 padded) whose stencil reads this block's
+ * rows or whose rows this block's stencil reads (two cells in y through the
+ * boundary rule); an item runs only after those blocks finished the
+ * previous stage.  Writes at most cap rows to table and the item count to
+ * *nitem (call with cap = 0 to size). */
+#define RSST_BATCH_PLAN_COLS 13
+int rsst_batch_plan(const rsst_config* boxes, int nbox, const int strip_rows[4], int* table, int cap,
+                    int* nitem);
+
+/* nsteps SSP-RK2 steps of every box of U_all, in place, enqueued on stream.
+ * 1 <= nsteps <= max_steps.  The first call (or a call with a different
+ * U_all, nsteps or strip rows) synchronises the stream, uploads the tables
+ * and captures the graph; later calls only launch it. */
+int rsst_batch_run(rsst_batch h, void* U_all, int nsteps, void* stream);
+
+/* Synchronises, then copies the time reached by every box into t[nbox]. */
+int rsst_batch_times(rsst_batch h, double* t, void* stream);
+
+/* As rsst_poll, for the batch. */
+int rsst_batch_poll(rsst_batch h, uint32_t* flags);
+
+int rsst_batch_destroy(rsst_batch h);
+
 /* Static string for a status code. */
 const char* rsst_strerror(int status);
 

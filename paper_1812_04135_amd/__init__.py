@@ -66,8 +66,21 @@ def lib():
         L.rsst_strerror.argtypes = [ctypes.c_int]
         L.rsst_strerror.restype = ctypes.c_char_p
         L.rsst_version.restype = ctypes.c_char_p
+        L.rsst_batch_init.argtypes = [ctypes.POINTER(rsst_config), ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_int64), ctypes.c_int, vp,
+                                      ctypes.POINTER(vp)]
+        L.rsst_batch_set_tiles.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+        L.rsst_batch_get_tiles.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+        L.rsst_batch_run.argtypes = [vp, vp, ctypes.c_int, vp]
+        L.rsst_batch_times.argtypes = [vp, dp, vp]
+        L.rsst_batch_poll.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32)]
+        L.rsst_batch_destroy.argtypes = [vp]
+        L.rsst_batch_plan.argtypes = [ctypes.POINTER(rsst_config), ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                      ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         for name in ("rsst_init", "rsst_prime", "rsst_step", "rsst_stage", "rsst_steps", "rsst_get_time",
-                     "rsst_diag", "rsst_poll", "rsst_destroy"):
+                     "rsst_diag", "rsst_poll", "rsst_destroy", "rsst_batch_init", "rsst_batch_set_tiles",
+                     "rsst_batch_get_tiles", "rsst_batch_run", "rsst_batch_times", "rsst_batch_poll",
+                     "rsst_batch_destroy", "rsst_batch_plan"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -223,6 +236,139 @@ class Solver:
     def close(self):
         if self.h is not None:
             rsst_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- batched boxes ----------------------------------------------------------
+
+def rsst_batch_init(cfgs, offsets, max_steps: int, stream=None) -> ctypes.c_void_p:
+    arr = (rsst_config * len(cfgs))(*cfgs)
+    off = (ctypes.c_int64 * len(offsets))(*[int(o) for o in offsets])
+    h = ctypes.c_void_p()
+    _check(lib().rsst_batch_init(arr, len(cfgs), off, int(max_steps), _stream(stream), ctypes.byref(h)),
+           "rsst_batch_init")
+    return h
+
+
+BATCH_PLAN_COLS = 13
+
+
+def rsst_batch_plan(cfgs, strip_rows=(16, 16, 16, 16)) -> np.ndarray:
+    """Host-only work-item table of a batch: rows (box, block, first row,
+    end row, ndep, dep[8]) -- see rsst.h."""
+    cs = [c if isinstance(c, rsst_config) else make_config(c) for c in cfgs]
+    arr = (rsst_config * len(cs))(*cs)
+    sr = (ctypes.c_int * 4)(*[int(x) for x in strip_rows])
+    n = ctypes.c_int()
+    _check(lib().rsst_batch_plan(arr, len(cs), sr, None, 0, ctypes.byref(n)), "rsst_batch_plan")
+    tab = np.zeros((n.value, BATCH_PLAN_COLS), dtype=np.int32)
+    _check(lib().rsst_batch_plan(arr, len(cs), sr, tab.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                 n.value, ctypes.byref(n)), "rsst_batch_plan")
+    return tab
+
+
+def rsst_batch_set_tiles(h, strip_rows):
+    a = (ctypes.c_int * 4)(*[int(x) for x in strip_rows])
+    _check(lib().rsst_batch_set_tiles(h, a), "rsst_batch_set_tiles")
+
+
+def rsst_batch_get_tiles(h):
+    a = (ctypes.c_int * 4)()
+    _check(lib().rsst_batch_get_tiles(h, a), "rsst_batch_get_tiles")
+    return list(a)
+
+
+def rsst_batch_run(h, U_all, nsteps: int, stream=None):
+    _check(lib().rsst_batch_run(h, _ptr(U_all), int(nsteps), _stream(stream)), "rsst_batch_run")
+
+
+def rsst_batch_times(h, nbox: int, stream=None) -> np.ndarray:
+    t = np.zeros(nbox)
+    _check(lib().rsst_batch_times(h, t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream(stream)),
+           "rsst_batch_times")
+    return t
+
+
+def rsst_batch_poll(h) -> int:
+    f = ctypes.c_uint32()
+    code = lib().rsst_batch_poll(h, ctypes.byref(f))
+    if code == RSST_E_NONPHYSICAL:
+        err = RsstError(code, "rsst_batch_poll")
+        err.flags = f.value
+        raise err
+    _check(code, "rsst_batch_poll")
+    return f.value
+
+
+def rsst_batch_destroy(h):
+    _check(lib().rsst_batch_destroy(h), "rsst_batch_destroy")
+
+
+class Batch:
+    """Many 2D boxes in one packed device array.
+
+    cfgs: per-box parameter dicts; for prec='fp32_pert' also a per-box FP64
+    background array [nvar, ny] (bg_axis 1) or [nvar, 1] (bg_axis -1).
+    Boxes are packed back to back in box order; pack()/unpack() convert
+    between per-box numpy arrays and the packed device tensor."""
+
+    def __init__(self, cfgs, prec="fp64", bgs=None, bg_axes=None, max_steps=256, stream=None):
+        import torch
+        self.cfgs = [dict(c) for c in cfgs]
+        self.prec = prec
+        self.nv = 4
+        self.shapes = [(self.nv, int(c["n"][1]), int(c["n"][0])) for c in cfgs]
+        sizes = [int(np.prod(sh)) for sh in self.shapes]
+        self.offsets = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+        self.total = int(sum(sizes))
+        self._bgs = None
+        cs = []
+        if prec == "fp32_pert":
+            self._bgs = [torch.from_numpy(np.ascontiguousarray(b, dtype=np.float64)).cuda() for b in bgs]
+            axes = bg_axes if bg_axes is not None else [1] * len(cfgs)
+            for c, b, a in zip(cfgs, self._bgs, axes):
+                cs.append(make_config(c, prec, b, a))
+        else:
+            for c in cfgs:
+                cs.append(make_config(c, prec))
+        self._cs = cs
+        self.dtype = torch.float32 if prec == "fp32_pert" else torch.float64
+        self.h = rsst_batch_init(cs, self.offsets, max_steps, stream)
+
+    def pack(self, arrays):
+        import torch
+        flat = np.concatenate([np.ascontiguousarray(a).ravel() for a in arrays])
+        np_dt = np.float32 if self.prec == "fp32_pert" else np.float64
+        return torch.from_numpy(flat.astype(np_dt)).cuda()
+
+    def unpack(self, U):
+        flat = U.detach().cpu().numpy()
+        return [flat[o:o + int(np.prod(sh))].reshape(sh) for o, sh in zip(self.offsets, self.shapes)]
+
+    def set_tiles(self, strip_rows):
+        rsst_batch_set_tiles(self.h, strip_rows)
+
+    def tiles(self):
+        return rsst_batch_get_tiles(self.h)
+
+    def run(self, U, nsteps, stream=None):
+        rsst_batch_run(self.h, U, nsteps, stream)
+
+    def times(self, stream=None):
+        return rsst_batch_times(self.h, len(self.cfgs), stream)
+
+    def poll(self):
+        return rsst_batch_poll(self.h)
+
+    def close(self):
+        if self.h is not None:
+            rsst_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -137,6 +137,7 @@ int rsst_init(const rsst_config* cfg, void* stream, rsst_handle* out) {
   a.bg = cfg->bg;
   a.bg_axis = cfg->prec == RSST_FP32_PERT ? cfg->bg_axis : -1;
   a.nbg = (a.bg_axis >= 0) ? cfg->n[a.bg_axis] : 1;
+  a.bg_uniform = (a.bg_axis == -1 || (cfg->ndim >= 2 && a.bg_axis == cfg->ndim - 1)) ? 1 : 0;
 
   h->npart = rsstk::diag_partials(h->ncell);
   const size_t ubytes = (size_t)h->nv * h->ncell * h->elem;

@@ -41,6 +41,7 @@ struct StageArgs {
   const double* bg;  // FP32 perturbation form: background [nv][nbg]
   int bg_axis;       // -1 uniform
   int nbg;
+  int bg_uniform;    // background index is workgroup-uniform (-1 or the march axis)
   int prec;          // 0 FP64, 1 FP32 perturbation
 };
 
