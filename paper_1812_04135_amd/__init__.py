@@ -98,8 +98,10 @@ def _check(code: int, where: str):
 
 
 def _stream(stream):
+    """A raw hipStream_t from None (torch's current stream), a torch stream
+    or an integer handle."""
     if stream is not None:
-        return ctypes.c_void_p(int(stream))
+        return ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
     import torch
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
@@ -339,6 +341,7 @@ class Batch:
                 cs.append(make_config(c, prec))
         self._cs = cs
         self.dtype = torch.float32 if prec == "fp32_pert" else torch.float64
+        self.max_steps = int(max_steps)
         self.h = rsst_batch_init(cs, self.offsets, max_steps, stream)
 
     def pack(self, arrays):
@@ -356,6 +359,11 @@ class Batch:
 
     def tiles(self):
         return rsst_batch_get_tiles(self.h)
+
+    def autotune(self, U, **kw):
+        """Measure and set the strip rows (see autotune.tune)."""
+        from . import autotune
+        return autotune.tune(self, U, **kw)
 
     def run(self, U, nsteps, stream=None):
         rsst_batch_run(self.h, U, nsteps, stream)

@@ -125,3 +125,31 @@ def test_batch_fp32_perturbation_stratified_boxes():
         err = max(float(np.abs(Ub[v].astype(np.float64) - pert[v]).max() / s[v]) for v in range(4))
         print(f"[batch fp32] box {q} n={cfg['n'][0]} err/|pert| = {err:.2e}", flush=True)
         assert err <= 1e-5, (q, err)
+
+
+def test_autotuner_sets_tiles_caches_and_keeps_results(tmp_path):
+    """The tuner leaves the caller's state untouched, writes its choice to the
+    JSON cache, reuses it on the next call, and the tuned run gives the same
+    bits as the default tiles (results do not depend on the strip rows)."""
+    from paper_1812_04135_amd import autotune
+    boxes = _boxes_fp64()
+    cache = str(tmp_path / "tiles.json")
+    B = R.Batch([c for c, _ in boxes], max_steps=8)
+    U0 = B.pack([u for _, u in boxes])
+    U = U0.clone()
+    tiles, ms, cached = B.autotune(U, nsteps=4, candidates=(8, 16, 32), reps=1, cache=cache)
+    assert not cached and ms > 0
+    assert torch.equal(U, U0)
+    assert B.tiles() == tiles
+    import json
+    db = json.load(open(cache))
+    assert db[autotune.batch_key(B)]["strip_rows"] == tiles
+    B.set_tiles([16, 16, 16, 16])
+    tiles2, _, cached2 = B.autotune(U, cache=cache)
+    assert cached2 and tiles2 == tiles and B.tiles() == tiles
+    B.run(U, 5)
+    torch.cuda.synchronize()
+    outs = B.unpack(U)
+    for q, ((cfg, U0n), Ub) in enumerate(zip(boxes, outs)):
+        Us, _ = _single(cfg, U0n, 5)
+        assert np.array_equal(Ub, Us), q
