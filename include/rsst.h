@@ -78,7 +78,14 @@ typedef struct rsst_config {
                         (nbg = n[bg_axis])                                    */
   double t_end;      /* > 0: the CFL step is cut so that t never passes t_end;
                         0: no end time                                        */
+  int flags;         /* or of rsst_flag                                       */
 } rsst_config;
+
+enum rsst_flag {
+  RSST_WITH_ADJOINT = 1  /* rsst_init also reserves the workspace of
+                            rsst_adjoint_step (FP64 only):
+                            nvar * ncell * (3 ndim + 3) doubles               */
+};
 
 typedef struct rsst_solver* rsst_handle;
 
@@ -129,6 +136,25 @@ int rsst_poll(rsst_handle h, uint32_t* flags);
 
 /* Frees the workspace.  The caller's arrays are untouched. */
 int rsst_destroy(rsst_handle h);
+
+/* ---- Adjoint -------------------------------------------------------------
+ * Discrete adjoint of one rsst_step of fixed dt (dt frozen: the CFL rule is
+ * not differentiated).  The step is U' = (U + U1 + dt R(U1)) / 2 with
+ * U1 = U + dt R(U), R the semi-discrete operator of Sec. 4.1 with the
+ * correction of the configured form (eq. pvs_dt, App. A) and gravity
+ * (App. B).  Given lam = dJ/dU' it computes, in place,
+ *   lam <- (dU'/dU)^T lam        and        *dJdxi += (dU'/dxi)^T lam,
+ * with the branch-frozen derivatives of the primal values: the MC limiter
+ * is 0 where l r <= 0, else it follows the first minimum of
+ * (|l+r|/2, 2|l|, 2|r|); the LLF speed is c_L where c_L >= c_R, else c_R;
+ * d|V| = 0 at V = 0.
+ * h: an FP64 handle made with flags & RSST_WITH_ADJOINT (else
+ * RSST_E_UNSUPPORTED).  U: device FP64 state at the start of the step (read
+ * only).  lam: device FP64 [nvar][ncell], in/out.  dt > 0: the dt the
+ * forward step used.  dJdxi: device double, accumulated.  U1 is recomputed
+ * in the handle's stage buffer, so the call must not fall between the two
+ * stages of a forward rsst_stage pair on the same handle.  Enqueues only. */
+int rsst_adjoint_step(rsst_handle h, const void* U, double* lam, double dt, double* dJdxi, void* stream);
 
 /* ---- Batched boxes ------------------------------------------------------
  * Many independent 2D boxes (each with its own size, xi, gravity, boundaries

@@ -21,6 +21,7 @@ RSST_E_NONPHYSICAL = -5
 FORMS = {"euler": 0, "pvs": 1, "pms": 2, "dvs": 3, "dms": 4, "pd": 5}
 BCS = {"periodic": 0, "reflect": 1}
 PRECS = {"fp64": 0, "fp32_pert": 1}
+RSST_WITH_ADJOINT = 1
 
 
 class rsst_config(ctypes.Structure):
@@ -40,6 +41,7 @@ class rsst_config(ctypes.Structure):
         ("bg", ctypes.c_void_p),
         ("bg_axis", ctypes.c_int),
         ("t_end", ctypes.c_double),
+        ("flags", ctypes.c_int),
     ]
 
 
@@ -75,12 +77,13 @@ def lib():
         L.rsst_batch_times.argtypes = [vp, dp, vp]
         L.rsst_batch_poll.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32)]
         L.rsst_batch_destroy.argtypes = [vp]
+        L.rsst_adjoint_step.argtypes = [vp, vp, vp, ctypes.c_double, vp, vp]
         L.rsst_batch_plan.argtypes = [ctypes.POINTER(rsst_config), ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                       ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         for name in ("rsst_init", "rsst_prime", "rsst_step", "rsst_stage", "rsst_steps", "rsst_get_time",
                      "rsst_diag", "rsst_poll", "rsst_destroy", "rsst_batch_init", "rsst_batch_set_tiles",
                      "rsst_batch_get_tiles", "rsst_batch_run", "rsst_batch_times", "rsst_batch_poll",
-                     "rsst_batch_destroy", "rsst_batch_plan"):
+                     "rsst_batch_destroy", "rsst_batch_plan", "rsst_adjoint_step"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -114,7 +117,7 @@ def _ptr(t) -> ctypes.c_void_p:
 
 
 def make_config(cfg: dict, prec: str = "fp64", bg=None, bg_axis: int = -1,
-                t_end: float = 0.0) -> rsst_config:
+                t_end: float = 0.0, adjoint: bool = False) -> rsst_config:
     """rsst_config from a plain parameter dict (the keys of the workloads module)."""
     c = rsst_config()
     c.ndim = int(cfg["ndim"])
@@ -139,6 +142,7 @@ def make_config(cfg: dict, prec: str = "fp64", bg=None, bg_axis: int = -1,
     c.bg = ctypes.c_void_p(bg.data_ptr()) if bg is not None else None
     c.bg_axis = int(bg_axis)
     c.t_end = float(t_end)
+    c.flags = RSST_WITH_ADJOINT if adjoint else 0
     return c
 
 
@@ -195,6 +199,11 @@ def rsst_destroy(h):
     _check(lib().rsst_destroy(h), "rsst_destroy")
 
 
+def rsst_adjoint_step(h, U, lam, dt: float, dJdxi, stream=None):
+    _check(lib().rsst_adjoint_step(h, _ptr(U), _ptr(lam), float(dt), _ptr(dJdxi), _stream(stream)),
+           "rsst_adjoint_step")
+
+
 def rsst_version() -> str:
     return lib().rsst_version().decode()
 
@@ -207,11 +216,11 @@ class Solver:
     background tensor bg [nvar, nbg])."""
 
     def __init__(self, cfg: dict, prec: str = "fp64", bg=None, bg_axis: int = -1,
-                 t_end: float = 0.0, stream=None):
+                 t_end: float = 0.0, stream=None, adjoint: bool = False):
         self.cfg = dict(cfg)
         self.prec = prec
         self._bg = bg  # keep the background alive as long as the handle
-        self._c = make_config(cfg, prec, bg, bg_axis, t_end)
+        self._c = make_config(cfg, prec, bg, bg_axis, t_end, adjoint)
         self.h = rsst_init(self._c, stream)
 
     def prime(self, U, t0=0.0, stream=None):
@@ -231,6 +240,11 @@ class Solver:
 
     def diag(self, U, stream=None):
         return rsst_diag(self.h, U, stream)
+
+    def adjoint_step(self, U, lam, dt, dJdxi, stream=None):
+        """lam <- (dU'/dU)^T lam for the fixed-dt step from U; dJdxi (a
+        1-element float64 CUDA tensor) += (dU'/dxi)^T lam."""
+        rsst_adjoint_step(self.h, U, lam, dt, dJdxi, stream)
 
     def poll(self):
         return rsst_poll(self.h)

@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "librsst.so")
-SOURCES = ["csrc/rsst_kernels.hip", "csrc/rsst_batch.hip", "csrc/rsst_api.hip"]
+SOURCES = ["csrc/rsst_kernels.hip", "csrc/rsst_batch.hip", "csrc/rsst_adjoint.hip", "csrc/rsst_api.hip"]
 
 # -packed-fp32-ops off: no packed FP32 instructions anywhere in the library
 HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -1,0 +1,28 @@
+// Internal interface of the adjoint kernels (rsst_adjoint.hip).  Not part of
+// the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace rsstk {
+
+struct AdjointPlan {
+  int ndim;
+  int n[3];
+  int refl_lo[3], refl_hi[3];
+  double inv_dx[3];
+  double g[3];
+  double gamma, xi;
+  int form;
+  long long ncell;
+  double* work;  // adjoint_workspace_doubles(ndim, ncell) doubles
+};
+
+size_t adjoint_workspace_doubles(int ndim, long long ncell);
+
+// lam <- (dU'/dU)^T lam for the step U -> U' of fixed dt, whose stage value
+// U1 = U + dt R(U) is given; dJdxi += (dU'/dxi)^T lam (device scalar).
+hipError_t launch_adjoint_step(const AdjointPlan& p, const double* U, const double* U1, double* lam, double dt,
+                               double* dJdxi, hipStream_t s);
+
+}  // namespace rsstk

@@ -1,0 +1,723 @@
+// Discrete adjoint of one SSP-RK2 RSST step, FP64, for a fixed dt.
+//
+// With U1 = U + dt R(U) and U' = (U + U1 + dt R(U1)) / 2 (Sec. 4.1, the
+// two-stage scheme), a cotangent lam' = dJ/dU' is pulled back by
+//   (a, s1) = VJP(U1, lam'),      mu  = (lam' + dt a) / 2,
+//   (b, s2) = VJP(U,  mu),        lam = lam'/2 + mu + dt b,
+//   dJ/dxi += dt s1 / 2 + dt s2,
+// where VJP(V, w) = (J_R(V)^T w, w . dR/dxi(V)) is the vector-Jacobian
+// product of the semi-discrete operator R: MC-limited face states on the
+// conservative variables, the LLF flux with c_tot = |V| + a/xi, the flux
+// divergence, the RSST correction of the chosen form (eq. pvs_dt and
+// App. A) and gravity (App. B).
+//
+// Derivatives are the branch-frozen ones of the primal values: the MC
+// limiter is zero when l r <= 0, else it follows the first minimum among
+// (|l+r|/2, 2|l|, 2|r|); the LLF speed is c_L when c_L >= c_R, else c_R;
+// d|V| = 0 at |V| = 0.  A reflecting wall is the mirror image S of the
+// cell state (normal momentum negated), so the wall face's outer state is
+// S of the inner face state and its cotangent returns through S.
+//
+// The VJP runs as five passes, each writing only its own cells, so the
+// result is deterministic (no atomics):
+//   A1 face   fluxes G = 2 Fhat at every face i+1/2 of every axis;
+//   A2 cell   increments Delta, reverse of correction + gravity:
+//             Delta_bar, the direct part of U_bar, the f part of xi_bar;
+//   A3 face   G_bar from Delta_bar, reverse of the LLF flux into the plus
+//             state of the left cell (Pb) and the minus state of the right
+//             cell (Mb), the alpha part of xi_bar;
+//   A4 cell   U_bar += Pb + Mb, reverse of the MC half slope h = (Pb-Mb):
+//             slope cotangents (lb, rb), stored over Pb and Mb;
+//   A5 cell   U_bar gathers -lb of the cell above and +rb of the cell below.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "rsst_adjoint.h"
+#include "rsst_device.h"
+
+#pragma clang fp contract(off)
+
+namespace rsstk {
+
+constexpr int kAdjThreads = 256;
+
+struct AdjArgs {
+  int ndim, nv;
+  int n[3];
+  int refl_lo[3], refl_hi[3];
+  long long ncell;
+  long long stride[3];  // cells between neighbours along each axis
+  double inv_dx[3];
+  double gamma, gm1, inv_gm1, inv_xi, f, dfdxi;
+  double g[3];
+  const double* V;   // primal state [nv][ncell]
+  const double* W;   // cotangent of R [nv][ncell]
+  double* out;       // J_R^T W [nv][ncell]
+  double* F;         // [ndim][nv][ncell] face fluxes G at i+1/2
+  double* Db;        // [nv][ncell]
+  double* Pb;        // [ndim][nv][ncell]
+  double* Mb;        // [ndim][nv][ncell]
+  double* xpart;     // [2][nblock] partial sums of xi_bar
+  int nblock;
+};
+
+__device__ __forceinline__ void cell_coords(const AdjArgs& A, long long c, int x[3]) {
+  x[0] = (int)(c % A.n[0]);
+  const long long r = c / A.n[0];
+  x[1] = (int)(r % A.n[1]);
+  x[2] = (int)(r / A.n[1]);
+}
+
+// Neighbour of cell c (coordinates x) at offset o in [-2, 2] along d under
+// the boundary rule; neg = the state there is the mirror image of the cell.
+__device__ __forceinline__ long long neighbour(const AdjArgs& A, long long c, const int x[3], int d, int o,
+                                               bool& neg) {
+  const int n = A.n[d];
+  int q = x[d] + o;
+  neg = false;
+  if (q < 0) {
+    if (A.refl_lo[d]) { neg = true; q = -1 - q; }
+    else q += n;
+  } else if (q >= n) {
+    if (A.refl_hi[d]) { neg = true; q = 2 * n - 1 - q; }
+    else q -= n;
+  }
+  return c + (long long)(q - x[d]) * A.stride[d];
+}
+
+template <int NV>
+__device__ __forceinline__ void load(const double* U, long long ncell, long long c, double (&u)[NV]) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v) u[v] = U[v * ncell + c];
+}
+
+template <int NV>
+__device__ __forceinline__ void load_nb(const AdjArgs& A, const double* U, long long c, const int x[3], int d,
+                                        int o, double (&u)[NV]) {
+  bool neg;
+  const long long q = neighbour(A, c, x, d, o, neg);
+  load<NV>(U, A.ncell, q, u);
+  if (neg) u[1 + d] = -u[1 + d];
+}
+
+// ---------------------------------------------------------------- reverse
+
+// dh/dl, dh/dr of the MC half slope h = MC(l, r)/2 with the tie rule above.
+__device__ __forceinline__ void mc_half_partials(double l, double r, double& dl, double& dr) {
+  dl = 0.0;
+  dr = 0.0;
+  if (l * r <= 0.0) return;
+  const double q1 = fabs(l + r) * 0.5, q2 = 2.0 * fabs(l), q3 = 2.0 * fabs(r);
+  if (q1 <= q2 && q1 <= q3) {
+    dl = 0.25;
+    dr = 0.25;
+  } else if (q2 <= q3) {
+    dl = 1.0;
+  } else {
+    dr = 1.0;
+  }
+}
+
+// Pulls back through the primitives of a state u: the cotangents of the
+// velocity vb and the pressure Pb are added into ub (V = m/rho,
+// P = (gamma-1)(E - |m|^2/(2 rho))).
+template <int NDIM>
+__device__ __forceinline__ void prim_pullback(const double (&u)[NDIM + 2], const double (&v)[NDIM], double ri,
+                                              double v2, const double (&vb)[NDIM], double Pb, double gm1,
+                                              double (&ub)[NDIM + 2]) {
+  constexpr int NV = NDIM + 2;
+#pragma unroll
+  for (int e = 0; e < NDIM; ++e) {
+    ub[1 + e] += vb[e] * ri - gm1 * v[e] * Pb;
+    ub[0] -= vb[e] * v[e] * ri;
+  }
+  ub[NV - 1] += gm1 * Pb;
+  ub[0] += gm1 * 0.5 * v2 * Pb;
+}
+
+// ub += J_F(u)^T Gb for the Euler flux along D, plus the pull-back of a
+// cotangent cb of c_tot = |V| + a/xi (xib collects dc/dxi cb).
+template <int NDIM, int D>
+__device__ __forceinline__ void flux_ctot_vjp(const double (&u)[NDIM + 2], const double (&Gb)[NDIM + 2], double cb,
+                                              double gamma, double gm1, double inv_xi, double (&ub)[NDIM + 2],
+                                              double& xib) {
+  constexpr int NV = NDIM + 2;
+  const double rho = u[0], ri = 1.0 / rho;
+  double v[NDIM], v2 = 0.0;
+#pragma unroll
+  for (int e = 0; e < NDIM; ++e) {
+    v[e] = u[1 + e] * ri;
+    v2 += v[e] * v[e];
+  }
+  const double P = gm1 * (u[NV - 1] - 0.5 * rho * v2);
+  double vb[NDIM];
+#pragma unroll
+  for (int e = 0; e < NDIM; ++e) vb[e] = 0.0;
+  double Pb = 0.0;
+  // F = (m_D, m_e v_D + P delta_eD, (E + P) v_D)
+  ub[1 + D] += Gb[0];
+#pragma unroll
+  for (int e = 0; e < NDIM; ++e) {
+    ub[1 + e] += Gb[1 + e] * v[D];
+    vb[D] += Gb[1 + e] * u[1 + e];
+  }
+  Pb += Gb[1 + D];
+  ub[NV - 1] += Gb[NV - 1] * v[D];
+  Pb += Gb[NV - 1] * v[D];
+  vb[D] += Gb[NV - 1] * (u[NV - 1] + P);
+  // c_tot = |V| + a / xi
+  if (cb != 0.0) {
+    const double vabs = sqrt(v2);
+    const double a = sqrt(gamma * P * ri);
+    if (vabs > 0.0) {
+#pragma unroll
+      for (int e = 0; e < NDIM; ++e) vb[e] += cb * v[e] / vabs;
+    }
+    const double ab = cb * inv_xi;
+    xib += -cb * a * inv_xi * inv_xi;
+    // a = sqrt(gamma P / rho): da = gamma/(2 a rho) dP - a/(2 rho) drho
+    Pb += ab * gamma / (2.0 * a * rho);
+    ub[0] -= ab * a / (2.0 * rho);
+  }
+  prim_pullback<NDIM>(u, v, ri, v2, vb, Pb, gm1, ub);
+}
+
+// Reverse of the corrected rate with gravity at one cell: given Rb, sets
+// Db = (dR/dDelta)^T Rb, adds (dR/du)^T Rb into ub and returns dR/df . Rb.
+template <int NDIM, int FORM>
+__device__ __forceinline__ double rate_vjp(const double (&u)[NDIM + 2], const double (&Dl)[NDIM + 2],
+                                           const double (&Rb)[NDIM + 2], const AdjArgs& A,
+                                           double (&Db)[NDIM + 2], double (&ub)[NDIM + 2]) {
+  constexpr int NV = NDIM + 2;
+  const double rho = u[0], ri = 1.0 / rho;
+  double v[NDIM], v2 = 0.0, vdm = 0.0;
+#pragma unroll
+  for (int e = 0; e < NDIM; ++e) {
+    v[e] = u[1 + e] * ri;
+    v2 += v[e] * v[e];
+    vdm += v[e] * Dl[1 + e];
+  }
+  const double P = A.gm1 * (u[NV - 1] - 0.5 * rho * v2);
+  const double H = (u[NV - 1] + P) * ri;
+  const double dP = A.gm1 * (0.5 * v2 * Dl[0] - vdm + Dl[NV - 1]);
+#pragma unroll
+  for (int q = 0; q < NV; ++q) Db[q] = Rb[q];
+  double vb[NDIM];
+#pragma unroll
+  for (int e = 0; e < NDIM; ++e) vb[e] = 0.0;
+  double Pb = 0.0, rhob = 0.0, Hb = 0.0, dPb = 0.0, fb = 0.0;
+  if constexpr (FORM == kPVS || FORM == kPMS || FORM == kDVS || FORM == kDMS) {
+    constexpr bool VEL = (FORM == kPVS || FORM == kDVS);  // correction vector (1, V, H)
+    double s, sb;
+    if constexpr (FORM == kPVS || FORM == kPMS) s = A.f * dP * rho / (A.gamma * P);
+    else s = A.f * Dl[0];
+    if constexpr (VEL) {
+      sb = -Rb[0] - H * Rb[NV - 1];
+#pragma unroll
+      for (int e = 0; e < NDIM; ++e) {
+        sb -= v[e] * Rb[1 + e];
+        vb[e] -= s * Rb[1 + e];
+      }
+      Hb = -s * Rb[NV - 1];
+    } else {  // (1, 0, H - |V|^2)
+      sb = -Rb[0] - (H - v2) * Rb[NV - 1];
+      Hb = -s * Rb[NV - 1];
+#pragma unroll
+      for (int e = 0; e < NDIM; ++e) vb[e] += 2.0 * s * Rb[NV - 1] * v[e];
+    }
+    if constexpr (FORM == kPVS || FORM == kPMS) {
+      const double k = rho / (A.gamma * P);
+      dPb = sb * A.f * k;
+      fb = sb * dP * k;
+      rhob += sb * A.f * dP / (A.gamma * P);
+      Pb -= sb * s / P;
+    } else {
+      Db[0] += A.f * sb;
+      fb = Dl[0] * sb;
+    }
+  } else if constexpr (FORM == kPD) {
+    dPb = -A.f * A.inv_gm1 * Rb[NV - 1];
+    fb = -A.inv_gm1 * dP * Rb[NV - 1];
+  }
+  if (dPb != 0.0) {
+    // dP = (gamma-1)(|V|^2/2 Delta rho - V.Delta m + Delta E)
+    Db[0] += A.gm1 * 0.5 * v2 * dPb;
+#pragma unroll
+    for (int e = 0; e < NDIM; ++e) {
+      Db[1 + e] -= A.gm1 * v[e] * dPb;
+      vb[e] += A.gm1 * (v[e] * Dl[0] - Dl[1 + e]) * dPb;
+    }
+    Db[NV - 1] += A.gm1 * dPb;
+  }
+  // H = (E + P) / rho
+  ub[NV - 1] += Hb * ri;
+  Pb += Hb * ri;
+  rhob -= Hb * H * ri;
+  // gravity: R_m += rho g, R_E += m.g
+#pragma unroll
+  for (int e = 0; e < NDIM; ++e) {
+    rhob += A.g[e] * Rb[1 + e];
+    ub[1 + e] += A.g[e] * Rb[NV - 1];
+  }
+  ub[0] += rhob;
+  prim_pullback<NDIM>(u, v, ri, v2, vb, Pb, A.gm1, ub);
+  return fb;
+}
+
+// ---------------------------------------------------------------- passes
+
+template <int NDIM>
+__device__ __forceinline__ void half_slope(const double (&um)[NDIM + 2], const double (&u0)[NDIM + 2],
+                                           const double (&up)[NDIM + 2], double (&h)[NDIM + 2]) {
+#pragma unroll
+  for (int v = 0; v < NDIM + 2; ++v) h[v] = mc_half(u0[v] - um[v], up[v] - u0[v]);
+}
+
+template <int NDIM, int D>
+__device__ __forceinline__ void face_pair(const AdjArgs& A, const Consts& K, long long c, const int x[3],
+                                          Face<NDIM + 2>& L, Face<NDIM + 2>& R, bool& wall_hi) {
+  constexpr int NV = NDIM + 2;
+  double um[NV], u0[NV], up[NV], upp[NV], h0[NV];
+  load_nb<NV>(A, A.V, c, x, D, -1, um);
+  load<NV>(A.V, A.ncell, c, u0);
+  load_nb<NV>(A, A.V, c, x, D, 1, up);
+  half_slope<NDIM>(um, u0, up, h0);
+  make_face<NDIM, D>(u0, h0, true, K, L);
+  wall_hi = A.refl_hi[D] && x[D] == A.n[D] - 1;
+  if (wall_hi) {
+    R = mirror<NDIM, D>(L);
+  } else {
+    double h1[NV];
+    load_nb<NV>(A, A.V, c, x, D, 2, upp);
+    half_slope<NDIM>(u0, up, upp, h1);
+    make_face<NDIM, D>(up, h1, false, K, R);
+  }
+}
+
+// Minus face state of a cell at a low wall and its mirror (the outer state).
+template <int NDIM, int D>
+__device__ __forceinline__ void wall_lo_pair(const AdjArgs& A, const Consts& K, long long c, const int x[3],
+                                             Face<NDIM + 2>& L, Face<NDIM + 2>& R) {
+  constexpr int NV = NDIM + 2;
+  double um[NV], u0[NV], up[NV], h0[NV];
+  load_nb<NV>(A, A.V, c, x, D, -1, um);
+  load<NV>(A.V, A.ncell, c, u0);
+  load_nb<NV>(A, A.V, c, x, D, 1, up);
+  half_slope<NDIM>(um, u0, up, h0);
+  make_face<NDIM, D>(u0, h0, false, K, R);
+  L = mirror<NDIM, D>(R);
+}
+
+template <int NDIM>
+__device__ __forceinline__ Consts adj_consts(const AdjArgs& A) {
+  return Consts{A.gamma, A.gm1, A.inv_gm1, A.inv_xi, A.f};
+}
+
+template <int NDIM, int D>
+__device__ __forceinline__ void a1_axis(const AdjArgs& A, const Consts& K, long long c, const int x[3]) {
+  constexpr int NV = NDIM + 2;
+  Face<NV> L, R;
+  bool wall;
+  face_pair<NDIM, D>(A, K, c, x, L, R, wall);
+  double G[NV];
+  flux2<NDIM, D>(L, R, G);
+  double* F = A.F + (long long)D * NV * A.ncell;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) F[v * A.ncell + c] = G[v];
+}
+
+template <int NDIM>
+__global__ void __launch_bounds__(kAdjThreads) adj_face_kernel(AdjArgs A) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= A.ncell) return;
+  int x[3];
+  cell_coords(A, c, x);
+  const Consts K = adj_consts<NDIM>(A);
+  a1_axis<NDIM, 0>(A, K, c, x);
+  if constexpr (NDIM >= 2) a1_axis<NDIM, 1>(A, K, c, x);
+  if constexpr (NDIM >= 3) a1_axis<NDIM, 2>(A, K, c, x);
+}
+
+__device__ __forceinline__ void block_partial(double v, double* out) {
+  __shared__ double red[kAdjThreads / 64];
+  const double w = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = w;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int q = 0; q < kAdjThreads / 64; ++q) s += red[q];
+    out[blockIdx.x] = s;
+  }
+}
+
+// G at the face below cell c along D (the face i-1/2).
+template <int NDIM, int D>
+__device__ __forceinline__ void flux_below(const AdjArgs& A, const Consts& K, long long c, const int x[3],
+                                           double (&G)[NDIM + 2]) {
+  constexpr int NV = NDIM + 2;
+  if (x[D] == 0 && A.refl_lo[D]) {
+    Face<NV> L, R;
+    wall_lo_pair<NDIM, D>(A, K, c, x, L, R);
+    flux2<NDIM, D>(L, R, G);
+  } else {
+    bool neg;
+    const long long q = neighbour(A, c, x, D, -1, neg);
+    const double* F = A.F + (long long)D * NV * A.ncell;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) G[v] = F[v * A.ncell + q];
+  }
+}
+
+template <int NDIM, int D>
+__device__ __forceinline__ void a2_axis(const AdjArgs& A, const Consts& K, long long c, const int x[3],
+                                        double (&Dl)[NDIM + 2]) {
+  constexpr int NV = NDIM + 2;
+  double Gl[NV];
+  flux_below<NDIM, D>(A, K, c, x, Gl);
+  const double* F = A.F + (long long)D * NV * A.ncell;
+  const double hd = 0.5 * A.inv_dx[D];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) Dl[v] -= (F[v * A.ncell + c] - Gl[v]) * hd;
+}
+
+template <int NDIM, int FORM>
+__global__ void __launch_bounds__(kAdjThreads) adj_cell_kernel(AdjArgs A) {
+  constexpr int NV = NDIM + 2;
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  double xib = 0.0;
+  if (c < A.ncell) {
+    int x[3];
+    cell_coords(A, c, x);
+    const Consts K = adj_consts<NDIM>(A);
+    double Dl[NV], u[NV], Rb[NV], Db[NV], ub[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      Dl[v] = 0.0;
+      ub[v] = 0.0;
+    }
+    a2_axis<NDIM, 0>(A, K, c, x, Dl);
+    if constexpr (NDIM >= 2) a2_axis<NDIM, 1>(A, K, c, x, Dl);
+    if constexpr (NDIM >= 3) a2_axis<NDIM, 2>(A, K, c, x, Dl);
+    load<NV>(A.V, A.ncell, c, u);
+    load<NV>(A.W, A.ncell, c, Rb);
+    const double fb = rate_vjp<NDIM, FORM>(u, Dl, Rb, A, Db, ub);
+    xib = fb * A.dfdxi;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      A.Db[v * A.ncell + c] = Db[v];
+      A.out[v * A.ncell + c] = ub[v];
+    }
+  }
+  block_partial(xib, A.xpart);
+}
+
+// Reverse of G = F(L) + F(R) - alpha (R - L): Lb, Rb and the xi part.
+template <int NDIM, int D>
+__device__ __forceinline__ void llf_vjp(const Face<NDIM + 2>& L, const Face<NDIM + 2>& R, const double (&Gb)[NDIM + 2],
+                                        const AdjArgs& A, double (&Lb)[NDIM + 2], double (&Rbar)[NDIM + 2],
+                                        double& xib) {
+  constexpr int NV = NDIM + 2;
+  const bool left = L.c >= R.c;
+  const double alpha = left ? L.c : R.c;
+  double ab = 0.0;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    Lb[v] = alpha * Gb[v];
+    Rbar[v] = -alpha * Gb[v];
+    ab -= Gb[v] * (R.u[v] - L.u[v]);
+  }
+  flux_ctot_vjp<NDIM, D>(L.u, Gb, left ? ab : 0.0, A.gamma, A.gm1, A.inv_xi, Lb, xib);
+  flux_ctot_vjp<NDIM, D>(R.u, Gb, left ? 0.0 : ab, A.gamma, A.gm1, A.inv_xi, Rbar, xib);
+}
+
+template <int NDIM, int D>
+__device__ __forceinline__ void mirror_add(double (&dst)[NDIM + 2], const double (&src)[NDIM + 2]) {
+#pragma unroll
+  for (int v = 0; v < NDIM + 2; ++v) dst[v] += (v == 1 + D) ? -src[v] : src[v];
+}
+
+template <int NDIM, int D>
+__device__ __forceinline__ void a3_axis(const AdjArgs& A, const Consts& K, long long c, const int x[3],
+                                        double& xib) {
+  constexpr int NV = NDIM + 2;
+  const double hd = 0.5 * A.inv_dx[D];
+  double* Pb = A.Pb + (long long)D * NV * A.ncell;
+  double* Mb = A.Mb + (long long)D * NV * A.ncell;
+  double d0[NV];
+  load<NV>(A.Db, A.ncell, c, d0);
+  {
+    // face i+1/2: dDelta_i/dG = -hd, dDelta_{i+1}/dG = +hd
+    Face<NV> L, R;
+    bool wall;
+    face_pair<NDIM, D>(A, K, c, x, L, R, wall);
+    double Gb[NV], Lb[NV], Rbar[NV];
+    if (wall) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Gb[v] = -hd * d0[v];
+    } else {
+      bool neg;
+      const long long q = neighbour(A, c, x, D, 1, neg);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Gb[v] = hd * (A.Db[v * A.ncell + q] - d0[v]);
+    }
+    llf_vjp<NDIM, D>(L, R, Gb, A, Lb, Rbar, xib);
+    if (wall) {
+      mirror_add<NDIM, D>(Lb, Rbar);
+    } else {
+      bool neg;
+      const long long q = neighbour(A, c, x, D, 1, neg);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Mb[v * A.ncell + q] = Rbar[v];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Pb[v * A.ncell + c] = Lb[v];
+  }
+  if (x[D] == 0 && A.refl_lo[D]) {
+    // wall face i-1/2: outer state S M_0, inner M_0; dDelta_0/dG = +hd
+    Face<NV> L, R;
+    wall_lo_pair<NDIM, D>(A, K, c, x, L, R);
+    double Gb[NV], Lb[NV], Rbar[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Gb[v] = hd * d0[v];
+    llf_vjp<NDIM, D>(L, R, Gb, A, Lb, Rbar, xib);
+    mirror_add<NDIM, D>(Rbar, Lb);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Mb[v * A.ncell + c] = Rbar[v];
+  }
+}
+
+template <int NDIM>
+__global__ void __launch_bounds__(kAdjThreads) adj_face_rev_kernel(AdjArgs A) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  double xib = 0.0;
+  if (c < A.ncell) {
+    int x[3];
+    cell_coords(A, c, x);
+    const Consts K = adj_consts<NDIM>(A);
+    a3_axis<NDIM, 0>(A, K, c, x, xib);
+    if constexpr (NDIM >= 2) a3_axis<NDIM, 1>(A, K, c, x, xib);
+    if constexpr (NDIM >= 3) a3_axis<NDIM, 2>(A, K, c, x, xib);
+  }
+  block_partial(xib, A.xpart + A.nblock);
+}
+
+template <int NDIM, int D>
+__device__ __forceinline__ void a4_axis(const AdjArgs& A, long long c, const int x[3], double (&ub)[NDIM + 2]) {
+  constexpr int NV = NDIM + 2;
+  double* Pb = A.Pb + (long long)D * NV * A.ncell;
+  double* Mb = A.Mb + (long long)D * NV * A.ncell;
+  double um[NV], u0[NV], up[NV];
+  load_nb<NV>(A, A.V, c, x, D, -1, um);
+  load<NV>(A.V, A.ncell, c, u0);
+  load_nb<NV>(A, A.V, c, x, D, 1, up);
+  const bool wlo = x[D] == 0 && A.refl_lo[D];
+  const bool whi = x[D] == A.n[D] - 1 && A.refl_hi[D];
+  double lb[NV], rb[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const double pb = Pb[v * A.ncell + c], mb = Mb[v * A.ncell + c];
+    const double hb = pb - mb;
+    double dl, dr;
+    mc_half_partials(u0[v] - um[v], up[v] - u0[v], dl, dr);
+    lb[v] = dl * hb;
+    rb[v] = dr * hb;
+    ub[v] += pb + mb + lb[v] - rb[v];
+    Pb[v * A.ncell + c] = lb[v];
+    Mb[v * A.ncell + c] = rb[v];
+  }
+  // a wall's ghost neighbour is S of this cell: its share comes back here
+  if (wlo) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ub[v] -= (v == 1 + D) ? -lb[v] : lb[v];
+  }
+  if (whi) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ub[v] += (v == 1 + D) ? -rb[v] : rb[v];
+  }
+}
+
+template <int NDIM>
+__global__ void __launch_bounds__(kAdjThreads) adj_slope_kernel(AdjArgs A) {
+  constexpr int NV = NDIM + 2;
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= A.ncell) return;
+  int x[3];
+  cell_coords(A, c, x);
+  double ub[NV];
+  load<NV>(A.out, A.ncell, c, ub);
+  a4_axis<NDIM, 0>(A, c, x, ub);
+  if constexpr (NDIM >= 2) a4_axis<NDIM, 1>(A, c, x, ub);
+  if constexpr (NDIM >= 3) a4_axis<NDIM, 2>(A, c, x, ub);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) A.out[v * A.ncell + c] = ub[v];
+}
+
+template <int NDIM, int D>
+__device__ __forceinline__ void a5_axis(const AdjArgs& A, long long c, const int x[3], double (&ub)[NDIM + 2]) {
+  constexpr int NV = NDIM + 2;
+  const double* lbv = A.Pb + (long long)D * NV * A.ncell;
+  const double* rbv = A.Mb + (long long)D * NV * A.ncell;
+  bool neg;
+  if (x[D] + 1 < A.n[D] || !A.refl_hi[D]) {  // l of the cell above is U_above - U_this
+    const long long q = neighbour(A, c, x, D, 1, neg);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ub[v] -= lbv[v * A.ncell + q];
+  }
+  if (x[D] > 0 || !A.refl_lo[D]) {  // r of the cell below is U_this - U_below
+    const long long q = neighbour(A, c, x, D, -1, neg);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ub[v] += rbv[v * A.ncell + q];
+  }
+}
+
+template <int NDIM>
+__global__ void __launch_bounds__(kAdjThreads) adj_gather_kernel(AdjArgs A) {
+  constexpr int NV = NDIM + 2;
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= A.ncell) return;
+  int x[3];
+  cell_coords(A, c, x);
+  double ub[NV];
+  load<NV>(A.out, A.ncell, c, ub);
+  a5_axis<NDIM, 0>(A, c, x, ub);
+  if constexpr (NDIM >= 2) a5_axis<NDIM, 1>(A, c, x, ub);
+  if constexpr (NDIM >= 3) a5_axis<NDIM, 2>(A, c, x, ub);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) A.out[v * A.ncell + c] = ub[v];
+}
+
+// mu = (lam + dt a) / 2
+__global__ void __launch_bounds__(kAdjThreads) adj_mu_kernel(const double* lam, const double* a, double* mu,
+                                                            double dt, long long n) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) mu[q] = 0.5 * (lam[q] + dt * a[q]);
+}
+
+// lam = lam / 2 + mu + dt b
+__global__ void __launch_bounds__(kAdjThreads) adj_lam_kernel(double* lam, const double* mu, const double* b,
+                                                             double dt, long long n) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) lam[q] = 0.5 * lam[q] + mu[q] + dt * b[q];
+}
+
+// dJdxi += dt/2 (sum of the U1 partials) + dt (sum of the U partials), in a
+// fixed order.  One workgroup.
+__global__ void __launch_bounds__(kAdjThreads) adj_xi_kernel(const double* p1, const double* p2, int m, double dt,
+                                                            double* dJdxi) {
+  __shared__ double red[2][kAdjThreads / 64];
+  double s1 = 0.0, s2 = 0.0;
+  for (int q = threadIdx.x; q < m; q += kAdjThreads) {
+    s1 += p1[q];
+    s2 += p2[q];
+  }
+  s1 = wave_sum(s1);
+  s2 = wave_sum(s2);
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = s1;
+    red[1][threadIdx.x >> 6] = s2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int q = 0; q < kAdjThreads / 64; ++q) {
+      a += red[0][q];
+      b += red[1][q];
+    }
+    *dJdxi += 0.5 * dt * a + dt * b;
+  }
+}
+
+template <int NDIM>
+static void* cell_kernel_ptr(int form) {
+  switch (form) {
+    case kEuler: return (void*)adj_cell_kernel<NDIM, kEuler>;
+    case kPVS: return (void*)adj_cell_kernel<NDIM, kPVS>;
+    case kPMS: return (void*)adj_cell_kernel<NDIM, kPMS>;
+    case kDVS: return (void*)adj_cell_kernel<NDIM, kDVS>;
+    case kDMS: return (void*)adj_cell_kernel<NDIM, kDMS>;
+    default: return (void*)adj_cell_kernel<NDIM, kPD>;
+  }
+}
+
+template <int NDIM>
+static hipError_t vjp_launch(AdjArgs A, int form, hipStream_t s) {
+  const dim3 grid(A.nblock), block(kAdjThreads);
+  hipLaunchKernelGGL(adj_face_kernel<NDIM>, grid, block, 0, s, A);
+  void* args[] = {(void*)&A};
+  hipError_t e = hipLaunchKernel(cell_kernel_ptr<NDIM>(form), grid, block, args, 0, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(adj_face_rev_kernel<NDIM>, grid, block, 0, s, A);
+  hipLaunchKernelGGL(adj_slope_kernel<NDIM>, grid, block, 0, s, A);
+  hipLaunchKernelGGL(adj_gather_kernel<NDIM>, grid, block, 0, s, A);
+  return hipGetLastError();
+}
+
+size_t adjoint_workspace_doubles(int ndim, long long ncell) {
+  const int nv = ndim + 2;
+  const long long nblock = (ncell + kAdjThreads - 1) / kAdjThreads;
+  // F, Pb, Mb: ndim fields each; Db, a/b, mu: one each; 4 partial arrays
+  return (size_t)nv * ncell * (3 * ndim + 3) + 4 * (size_t)nblock;
+}
+
+hipError_t launch_adjoint_step(const AdjointPlan& p, const double* U, const double* U1, double* lam, double dt,
+                               double* dJdxi, hipStream_t s) {
+  const int ndim = p.ndim, nv = ndim + 2;
+  const long long n = p.ncell, nf = (long long)nv * n;
+  const int nblock = (int)((n + kAdjThreads - 1) / kAdjThreads);
+  double* w = p.work;
+  AdjArgs A{};
+  A.ndim = ndim;
+  A.nv = nv;
+  for (int d = 0; d < 3; ++d) {
+    A.n[d] = p.n[d];
+    A.refl_lo[d] = p.refl_lo[d];
+    A.refl_hi[d] = p.refl_hi[d];
+    A.inv_dx[d] = p.inv_dx[d];
+    A.g[d] = p.g[d];
+  }
+  A.stride[0] = 1;
+  A.stride[1] = p.n[0];
+  A.stride[2] = (long long)p.n[0] * p.n[1];
+  A.ncell = n;
+  A.gamma = p.gamma;
+  A.gm1 = p.gamma - 1.0;
+  A.inv_gm1 = 1.0 / (p.gamma - 1.0);
+  A.inv_xi = 1.0 / p.xi;
+  A.f = 1.0 - 1.0 / (p.xi * p.xi);
+  A.dfdxi = 2.0 / (p.xi * p.xi * p.xi);
+  A.F = w;
+  A.Pb = A.F + ndim * nf;
+  A.Mb = A.Pb + ndim * nf;
+  A.Db = A.Mb + ndim * nf;
+  double* ab = A.Db + nf;
+  double* mu = ab + nf;
+  double* part1 = mu + nf;
+  double* part2 = part1 + 2 * nblock;
+  A.nblock = nblock;
+  const dim3 eg((unsigned)((nf + kAdjThreads - 1) / kAdjThreads)), eb(kAdjThreads);
+  auto vjp = [&](const double* V, const double* Wc, double* out, double* part) {
+    A.V = V;
+    A.W = Wc;
+    A.out = out;
+    A.xpart = part;
+    switch (ndim) {
+      case 1: return vjp_launch<1>(A, p.form, s);
+      case 2: return vjp_launch<2>(A, p.form, s);
+      default: return vjp_launch<3>(A, p.form, s);
+    }
+  };
+  // (a, s1) = VJP(U1, lam); mu = (lam + dt a)/2
+  hipError_t e = vjp(U1, lam, ab, part1);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(adj_mu_kernel, eg, eb, 0, s, lam, ab, mu, dt, nf);
+  // (b, s2) = VJP(U, mu); lam = lam/2 + mu + dt b
+  e = vjp(U, mu, ab, part2);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(adj_lam_kernel, eg, eb, 0, s, lam, mu, ab, dt, nf);
+  // each VJP left partials of the f part then the alpha part: 2 nblock each
+  hipLaunchKernelGGL(adj_xi_kernel, dim3(1), eb, 0, s, part1, part2, 2 * nblock, dt, dJdxi);
+  return hipGetLastError();
+}
+
+}  // namespace rsstk

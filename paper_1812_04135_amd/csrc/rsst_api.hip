@@ -12,6 +12,7 @@
 #include <new>
 
 #include "rsst.h"
+#include "rsst_adjoint.h"
 #include "rsst_internal.h"
 
 using rsstk::Geometry;
@@ -30,6 +31,7 @@ struct rsst_solver {
   double* diag_out;  // 8 doubles, owned
   int npart;
   bool primed;
+  double* adj_work;  // adjoint workspace (flags & RSST_WITH_ADJOINT), owned
 };
 
 static int check(hipError_t e) { return e == hipSuccess ? RSST_OK : RSST_E_DEVICE; }
@@ -60,6 +62,8 @@ static int validate(const rsst_config* c) {
     if (c->bg_axis < -1 || c->bg_axis >= c->ndim) return RSST_E_ARG;
   }
   if (!(c->t_end >= 0.0) || !std::isfinite(c->t_end)) return RSST_E_ARG;
+  if (c->flags & ~RSST_WITH_ADJOINT) return RSST_E_ARG;
+  if ((c->flags & RSST_WITH_ADJOINT) && c->prec != RSST_FP64) return RSST_E_UNSUPPORTED;
   // fields are addressed with 32-bit byte offsets
   {
     const long long cells = (long long)c->n[0] * c->n[1] * c->n[2];
@@ -148,6 +152,15 @@ int rsst_init(const rsst_config* cfg, void* stream, rsst_handle* out) {
     (void)hipFree(h->u1); (void)hipFree(h->scal); (void)hipFree(h->part); (void)hipFree(h->diag_out);
     delete h;
     return RSST_E_NOMEM;
+  }
+  h->adj_work = nullptr;
+  if (cfg->flags & RSST_WITH_ADJOINT) {
+    const size_t nd = rsstk::adjoint_workspace_doubles(cfg->ndim, h->ncell);
+    if (hipMalloc((void**)&h->adj_work, nd * sizeof(double)) != hipSuccess) {
+      h->adj_work = nullptr;
+      rsst_destroy(h);
+      return RSST_E_NOMEM;
+    }
   }
   if (hipMemsetAsync(h->scal, 0, rsstk::kNumScalars * sizeof(double), s) != hipSuccess) {
     rsst_destroy(h);
@@ -249,8 +262,38 @@ int rsst_destroy(rsst_handle h) {
   (void)hipFree(h->scal);
   (void)hipFree(h->part);
   (void)hipFree(h->diag_out);
+  if (h->adj_work) (void)hipFree(h->adj_work);
   delete h;
   return RSST_OK;
+}
+
+int rsst_adjoint_step(rsst_handle h, const void* U, double* lam, double dt, double* dJdxi, void* stream) {
+  if (!h || !U || !lam || !dJdxi || !(dt > 0.0) || !std::isfinite(dt)) return RSST_E_ARG;
+  if (!h->adj_work) return RSST_E_UNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  // U1 = U + dt R(U), the same stage-1 kernel as the forward step
+  StageArgs a = h->args;
+  a.dt_fixed = dt;
+  a.uin = U;
+  a.un = nullptr;
+  a.uout = h->u1;
+  if (rsstk::launch_stage(a, 1, s) != hipSuccess) return RSST_E_DEVICE;
+  const rsst_config& c = h->cfg;
+  rsstk::AdjointPlan p{};
+  p.ndim = c.ndim;
+  for (int d = 0; d < 3; ++d) {
+    p.n[d] = c.n[d];
+    p.refl_lo[d] = d < c.ndim && c.bc_lo[d] == RSST_REFLECT;
+    p.refl_hi[d] = d < c.ndim && c.bc_hi[d] == RSST_REFLECT;
+    p.inv_dx[d] = d < c.ndim ? 1.0 / c.dx[d] : 0.0;
+    p.g[d] = d < c.ndim ? c.g[d] : 0.0;
+  }
+  p.gamma = c.gamma;
+  p.xi = c.xi;
+  p.form = c.form;
+  p.ncell = h->ncell;
+  p.work = h->adj_work;
+  return check(rsstk::launch_adjoint_step(p, (const double*)U, (const double*)h->u1, lam, dt, dJdxi, s));
 }
 
 }  // extern "C"

@@ -227,4 +227,12 @@ __device__ __forceinline__ double wave_max(double x) {
   return x;
 }
 
+// Butterfly sum over the wave: every lane ends with the same value, formed
+// in the same order on every run.
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x = x + __shfl_xor(x, o, 64);
+  return x;
+}
+
 }  // namespace rsstk

@@ -1,0 +1,78 @@
+"""Differentiable multi-step RSST rollout for PyTorch (FP64).
+
+RSSTRollout.apply(U0, xi, cfg, nsteps, dt, checkpoint_every) runs nsteps
+fixed-dt SSP-RK2 steps of the library from U0 and returns the final state.
+Its backward pulls the incoming gradient back through every step with the
+hand-written adjoint (rsst_adjoint_step), giving dJ/dU0 and dJ/dxi.  The
+forward keeps only the states at every checkpoint_every-th step; the
+backward re-runs each segment forward from its checkpoint (device tensors
+only) and then runs the segment's adjoint steps in reverse.
+
+The time step is frozen: dt is an input, not the CFL rule, so the gradient
+is that of the map U0 -> U_N at fixed dt.  Every step, forward and adjoint,
+runs in the library's kernels; this module orders the calls and owns the
+checkpoint tensors.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import Solver
+
+
+class RSSTRollout(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, U0, xi, cfg, nsteps, dt, checkpoint_every=20):
+        if U0.dtype != torch.float64 or not U0.is_cuda:
+            raise TypeError("RSSTRollout: U0 must be a float64 CUDA tensor")
+        nsteps, K = int(nsteps), max(1, int(checkpoint_every))
+        c = dict(cfg)
+        c["xi"] = float(xi)
+        solver = Solver(c, adjoint=True)
+        U = U0.detach().contiguous().clone()
+        ckpts = [U.clone()]
+        for n in range(nsteps):
+            solver.step(U, dt)
+            if (n + 1) % K == 0 and n + 1 < nsteps:
+                ckpts.append(U.clone())
+        ctx.solver, ctx.ckpts, ctx.nsteps, ctx.dt, ctx.K = solver, ckpts, nsteps, float(dt), K
+        ctx.xi_needs_grad = isinstance(xi, torch.Tensor) and xi.requires_grad
+        return U
+
+    @staticmethod
+    def backward(ctx, gU):
+        solver, K, dt, nsteps = ctx.solver, ctx.K, ctx.dt, ctx.nsteps
+        lam = gU.detach().to(torch.float64).contiguous().clone()
+        dxi = torch.zeros(1, dtype=torch.float64, device=lam.device)
+        nseg = len(ctx.ckpts)
+        for seg in reversed(range(nseg)):
+            n0, n1 = seg * K, min((seg + 1) * K, nsteps)
+            states = [ctx.ckpts[seg].clone()]
+            for _ in range(n0, n1 - 1):
+                u = states[-1].clone()
+                solver.step(u, dt)
+                states.append(u)
+            for n in reversed(range(n0, n1)):
+                solver.adjoint_step(states[n - n0], lam, dt, dxi)
+            del states
+        solver.close()
+        ctx.ckpts = None
+        gxi = dxi.reshape(()) if ctx.xi_needs_grad else None
+        return lam, gxi, None, None, None, None
+
+
+def rollout(U0, xi, cfg, nsteps, dt, checkpoint_every=20):
+    """Final state of nsteps fixed-dt steps from U0 (differentiable in U0
+    and, if xi is a tensor that requires grad, in xi)."""
+    return RSSTRollout.apply(U0, xi, cfg, nsteps, dt, checkpoint_every)
+
+
+def kinetic_energy(U, cfg):
+    """Domain integral of |m|^2 / (2 rho), the final-state functional of the
+    adjoint workload."""
+    ndim = int(cfg["ndim"])
+    vol = 1.0
+    for d in range(ndim):
+        vol *= float(cfg["dx"][d])
+    m2 = sum(U[1 + d] ** 2 for d in range(ndim))
+    return 0.5 * (m2 / U[0]).sum() * vol

@@ -88,8 +88,22 @@ def test_unsupported_shape_reported():
     assert R.lib().rsst_init(ctypes.byref(c), None, ctypes.byref(h)) == -4
 
 
+def test_adjoint_flags_validated_on_host():
+    cfg, _ = W.random_state(2, [16, 12])
+    h = ctypes.c_void_p()
+    c = R.make_config(cfg)
+    c.flags = 4  # unknown flag bit
+    assert R.lib().rsst_init(ctypes.byref(c), None, ctypes.byref(h)) == -1
+    # the adjoint is FP64 only
+    c = R.make_config(cfg, prec="fp32_pert", bg=None, adjoint=True)
+    c.bg = ctypes.c_void_p(8)  # never dereferenced: rejected before any device call
+    assert R.lib().rsst_init(ctypes.byref(c), None, ctypes.byref(h)) == -4
+    assert not h.value
+
+
 def test_null_arguments():
     L = R.lib()
+    assert L.rsst_adjoint_step(None, None, None, ctypes.c_double(0.1), None, None) == -1
     assert L.rsst_step(None, None, ctypes.c_double(0.0), None) == -1
     assert L.rsst_poll(None, None) == -1
     assert L.rsst_destroy(None) == -1
