@@ -171,7 +171,8 @@ def test_rollout_checkpointing_and_oracle_directional_derivatives():
 def test_finite_differences_of_kinetic_energy_bubble():
     """The adjoint workload at reduced size: bubble with xi = 10, gradient of
     the final kinetic energy w.r.t. the initial density field and xi, against
-    central differences (h = 1e-6) on smooth directions."""
+    central differences (h = 1e-6 on the density, 1e-4 xi on xi) on smooth
+    directions."""
     from paper_1812_04135_amd.rollout import kinetic_energy, rollout
     cfg, U0, meta = W.adjoint2d(n=64, ndir=4)
     nsteps = 40
