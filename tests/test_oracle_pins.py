@@ -334,6 +334,42 @@ def test_cfl_dt_closed_form():
     assert abs(oracle.cfl_dt(cfg, U) - 0.4 * (1.0 / 16) / c) <= 1e-15
 
 
+def test_diagnostics_closed_form_and_brute_force():
+    """Volume-weighted sums, kinetic energy, max |V| and max xi |V| / a: a
+    uniform state against closed forms, then a two-level state (half the
+    cells at each of two known states) against the same closed forms."""
+    n = [8, 6, 4]
+    L = [1.0, 3.0, 0.5]
+    cfg = W.base_cfg(3, n, xi=7.0, length=L)
+    shape = tuple(reversed(n))
+    vol = L[0] * L[1] * L[2]
+    rho, P, V = 1.7, 2.2, np.array([0.25, -0.5, 0.125])
+    U = W.conservative(np.full(shape, rho), [np.full(shape, v) for v in V], np.full(shape, P))
+    out = oracle.diag(cfg, U)
+    a = math.sqrt(GAMMA * P / rho)
+    ke = 0.5 * rho * float(V @ V)
+    E = P / (GAMMA - 1) + ke
+    want = [rho * vol, *(rho * V * vol), E * vol, ke * vol, float(np.linalg.norm(V)),
+            7.0 * float(np.linalg.norm(V)) / a]
+    np.testing.assert_allclose(out, want, rtol=1e-14, atol=1e-15)
+    # two states on alternating x columns: sums are the averages times the volume
+    rho2, P2, V2 = 0.4, 0.9, np.array([-1.0, 0.0, 0.75])
+    mask = (np.arange(n[0]) % 2 == 1)[None, None, :] * np.ones(shape, dtype=bool)
+    r = np.where(mask, rho2, rho)
+    p = np.where(mask, P2, P)
+    vs = [np.where(mask, V2[d], V[d]) for d in range(3)]
+    U = W.conservative(r, vs, p)
+    out = oracle.diag(cfg, U)
+    a2 = math.sqrt(GAMMA * P2 / rho2)
+    ke2 = 0.5 * rho2 * float(V2 @ V2)
+    E2 = P2 / (GAMMA - 1) + ke2
+    half = 0.5 * vol
+    want = [(rho + rho2) * half, *((rho * V + rho2 * V2) * half), (E + E2) * half, (ke + ke2) * half,
+            max(np.linalg.norm(V), np.linalg.norm(V2)),
+            7.0 * max(np.linalg.norm(V) / a, np.linalg.norm(V2) / a2)]
+    np.testing.assert_allclose(out, want, rtol=1e-13, atol=1e-15)
+
+
 def _sums(cfg, U):
     return np.array([U[v].sum() for v in range(U.shape[0])])
 
