@@ -58,16 +58,18 @@ __device__ __forceinline__ double sqrt_nr(double x) {
 
 // Half of the monotonized-central limited slope (Sec. 4.1, item 2):
 //   MC(l, r) = 0 if l r <= 0, else sign(l+r) min(|l+r|/2, 2|l|, 2|r|).
-// With s = sign(l) this is s max(0, min(2|l|, s(l+r)/2, 2 s r)); the
+// With s = sign(l) (as +-1.0) this is s max(0, min(2|l|, s(l+r)/2, 2 s r)); the
 // function returns MC/2 = s max(0, min(|l|, s r, (|l| + s r)/4)), which is
 // the offset of the face states from the cell value.  On the l r > 0 branch
 // |l| + |r| = |l + r| exactly, so the result equals MC/2 bit for bit.
+// Multiplying by s = +-1 is exact and keeps every min/max operand an
+// arithmetic result (no NaN-quieting of bit-built operands).
 __device__ __forceinline__ double mc_half(double l, double r) {
-  const int sgn = __double2hiint(l) & 0x80000000;
-  const double sr = __hiloint2double(__double2hiint(r) ^ sgn, __double2loint(r));
+  const double s = __hiloint2double((__double2hiint(l) & 0x80000000) | 0x3ff00000, 0);
+  const double sr = s * r;
   const double al = fabs(l);
   const double h = fmax(fmin(fmin(al, sr), 0.25 * (al + sr)), 0.0);
-  return __hiloint2double(__double2hiint(h) | sgn, __double2loint(h));
+  return s * h;
 }
 
 // Primitive recovery of a face state, normal axis D (Sec. 3.2 and 4.1):
@@ -207,17 +209,19 @@ __device__ __forceinline__ double cell_ctot(const double (&u)[NDIM + 2], const C
 
 // ---- cross-lane moves (wave64 DPP) -------------------------------------
 
-// Value held by lane l-1 (lane 0 receives 0).
+// Value held by lane l-1 (lane 0 receives 0: with bound_ctrl set the
+// hardware writes 0 where the source lane is outside the wave, so no
+// zeroed destination has to be prepared).
 __device__ __forceinline__ double from_left(double x) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x138, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x138, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0x138, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0x138, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
 
 // Value held by lane l+1 (lane 63 receives 0).
 __device__ __forceinline__ double from_right(double x) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x130, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x130, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0x130, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0x130, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
 

@@ -243,6 +243,14 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
     jj = map_index(j0 + ts_eff + 1, G.ns, A.bc_lo[1], A.bc_hi[1], n); nhi2 = n ? 2 : -1; chi2 = (jj * G.nx + i) * SZ;
     bhi2 = (A.bg_axis == 1) ? jj : bgi_xy;
   }
+  // An edge row of a tile with at least two rows reads the two rows outside
+  // its side one plane ahead, so their load latency hides behind a whole
+  // plane of work; a one-row tile (both sides) loads them when needed.
+  const bool pre = HS && (first_row != last_row);
+  const int oc1 = first_row ? clo1 : chi1, oc2 = first_row ? clo2 : chi2;
+  const int on1 = first_row ? nlo1 : nhi1, on2 = first_row ? nlo2 : nhi2;
+  const int ob1 = first_row ? blo1 : bhi1, ob2 = first_row ? blo2 : bhi2;
+  double o1[NV], o2[NV];
 
   double q0[NV], q1[NV], sm0[NV], Fm_lo[NV];
   double cmax = 0.0;
@@ -270,6 +278,10 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
     flux2<NDIM, DM>(fl, fr, Fm_lo);
   } else {
     load_cell<NDIM, ST>(A, uin, 0, col, -1, bgi_xy, q0);
+  }
+  if (pre) {
+    load_cell<NDIM, ST>(A, uin, k0l * plane, oc1, on1, bg_on_m ? k0l : ob1, o1);
+    load_cell<NDIM, ST>(A, uin, k0l * plane, oc2, on2, bg_on_m ? k0l : ob2, o2);
   }
 
   for (int it = 0; it < G.km; ++it) {
@@ -360,13 +372,19 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
     Face<NV> fym;
     if constexpr (HS) {
       double uD[NV], uU[NV], h[NV];
-      if (first_row) {
+      if (first_row && pre) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) uD[v] = o1[v];
+      } else if (first_row) {
         load_cell<NDIM, ST>(A, uin, koff, clo1, nlo1, bg_on_m ? k : blo1, uD);
       } else {
 #pragma unroll
         for (int v = 0; v < NV; ++v) uD[v] = Urow[(v * TS + row - 1) * nxp + i_raw];
       }
-      if (last_row) {
+      if (last_row && pre) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) uU[v] = o1[v];
+      } else if (last_row) {
         load_cell<NDIM, ST>(A, uin, koff, chi1, nhi1, bg_on_m ? k : bhi1, uU);
       } else {
         const int ru = min(row + 1, TS - 1);  // idle rows past the tile read in range
@@ -383,7 +401,12 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
           // minus state of the row above the tile, and the flux at the
           // tile's upper face
           double u2[NV], hh[NV], Fh[NV];
-          load_cell<NDIM, ST>(A, uin, koff, chi2, nhi2, bg_on_m ? k : bhi2, u2);
+          if (pre) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) u2[v] = o2[v];
+          } else {
+            load_cell<NDIM, ST>(A, uin, koff, chi2, nhi2, bg_on_m ? k : bhi2, u2);
+          }
 #pragma unroll
           for (int v = 0; v < NV; ++v) hh[v] = mc_half(uU[v] - q0[v], u2[v] - uU[v]);
           Face<NV> fh;
@@ -398,7 +421,12 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
         // plus state of the row below the tile, and the flux at the tile's
         // lower face
         double u2[NV], hh[NV], Fh[NV];
-        load_cell<NDIM, ST>(A, uin, koff, clo2, nlo2, bg_on_m ? k : blo2, u2);
+        if (pre) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) u2[v] = o2[v];
+        } else {
+          load_cell<NDIM, ST>(A, uin, koff, clo2, nlo2, bg_on_m ? k : blo2, u2);
+        }
 #pragma unroll
         for (int v = 0; v < NV; ++v) hh[v] = mc_half(uD[v] - u2[v], q0[v] - uD[v]);
         Face<NV> fh;
@@ -407,6 +435,11 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
 #pragma unroll
         for (int v = 0; v < NV; ++v) Frow[(v * (TS + 1)) * nxp + i_raw] = Fh[v];
       }
+    }
+    if (pre) {  // the outside rows of the next plane
+      const int kn = min(kraw + 1, G.nm - 1);
+      load_cell<NDIM, ST>(A, uin, kn * plane, oc1, on1, bg_on_m ? kn : ob1, o1);
+      load_cell<NDIM, ST>(A, uin, kn * plane, oc2, on2, bg_on_m ? kn : ob2, o2);
     }
     __syncthreads();  // B2
 
