@@ -333,7 +333,7 @@ def main():
         "speedup_vs_fp64": round(ms_step / ms32, 3)}
 
     # 2D bubble 512^2 FP64 (L2/MALL resident; launch-latency sensitive)
-    cfg2, U2_0, _ = W.bubble2d()
+    cfg2, U2_0, meta2 = W.bubble2d()
     U2 = torch.from_numpy(U2_0).to(dev)
     s2 = R.Solver(cfg2)
     ms2 = timed(s2, U2, 200)
@@ -341,6 +341,21 @@ def main():
     n2 = U2_0[0].size
     sec["bubble2d_512_fp64"] = {"ms_per_step": round(ms2, 5),
                                 "Gcell_updates_s": round(n2 / (ms2 * 1e-3) / 1e9, 4)}
+    # the same bubble as an FP32 perturbation about the uniform ambient state
+    bg2 = torch.from_numpy(meta2["bg"]).to(dev)
+    U2p0 = (U2_0 - meta2["bg"][:, :, None]).astype(np.float32)
+    U2p = torch.from_numpy(U2p0).to(dev)
+    s2p = R.Solver(cfg2, prec="fp32_pert", bg=bg2, bg_axis=-1)
+    ms2p = timed(s2p, U2p, 200)
+    s2p.close()
+    sec["bubble2d_512_fp32_pert"] = {"ms_per_step": round(ms2p, 5),
+                                     "Gcell_updates_s": round(n2 / (ms2p * 1e-3) / 1e9, 4),
+                                     "speedup_vs_fp64": round(ms2 / ms2p, 3)}
+    # FP64 diagnostics (sums, kinetic energy, maxima) of the 256^3 state
+    td = time.perf_counter()
+    for _ in range(20):
+        sol.diag(U)
+    sec["diag_strat3d_256_ms"] = round((time.perf_counter() - td) / 20 * 1e3, 4)
 
     # 1D wave, 256 cells, xi = 10, the whole run to t_end (2 reduced crossings)
     cfg1, U1w, meta1 = W.wave1d(xi=10.0)
@@ -394,11 +409,35 @@ def main():
         err32 = max(float(np.abs(g32[v] - pert[v]).max() / sc[v]) for v in range(nv))
         s.close()
         out["secondary"]["strat3d_fp32_pert"]["err_vs_oracle_pert"] = err32
+        # the bubble's FP32 perturbation over 5 steps against the FP64 oracle
+        Uo2, _, _ = oracle.run(cfg2, meta2["bg"][:, :, None] + U2p0.astype(np.float64), 5)
+        g2 = torch.from_numpy(U2p0).to(dev)
+        s = R.Solver(cfg2, prec="fp32_pert", bg=bg2, bg_axis=-1)
+        s.steps(g2, 5)
+        torch.cuda.synchronize()
+        s.close()
+        out["secondary"]["bubble2d_512_fp32_pert"]["err_vs_oracle_pert"] = pert_err(
+            g2.cpu().numpy().astype(np.float64), Uo2 - meta2["bg"][:, :, None], 4)
+        out["secondary"]["bubble2d_512_fp32_pert"]["err_steps"] = 5
+        # the same oracle on one core, on a smaller bounded sample: one step
+        # of a 256 x 256 x 32 slab of the box (same columns, bottom 32 planes)
+        nth = oracle.threads()
+        oracle.set_threads(1)
+        cfg1 = dict(cfg)
+        cfg1["n"] = [256, 256, 32]
+        U1c = np.ascontiguousarray(U0[:, :32])
+        t1 = time.perf_counter()
+        oracle.run(cfg1, U1c, 1)
+        one_s = time.perf_counter() - t1
+        oracle.set_threads(nth)
         out["cpu_baseline"] = {"value": round(ncell * args.cpu_steps / cpu_s / 1e9, 6),
-                               "unit": "Gcell-updates/s", "cores": oracle.threads(),
+                               "unit": "Gcell-updates/s", "cores": nth,
                                "kind": "oracle",
                                "sample": f"{args.cpu_steps} full steps of the 256^3 box "
-                                         f"({cpu_s:.1f} s)"}
+                                         f"({cpu_s:.1f} s)",
+                               "one_core": {"value": round(256 * 256 * 32 / one_s / 1e9, 6),
+                                            "cores": 1,
+                                            "sample": f"1 step of a 256x256x32 slab ({one_s:.1f} s)"}}
         out["err_vs_oracle"] = {"max_err_over_scale": err, "steps": args.cpu_steps,
                                 "tolerance": 1e-12}
     sol.close()

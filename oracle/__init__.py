@@ -83,6 +83,7 @@ def _load():
         lib.ora_run_tangent.restype = ctypes.c_int64
         lib.ora_diag.argtypes = [cp, dp, dp]
         lib.ora_threads.restype = ctypes.c_int
+        lib.ora_set_threads.argtypes = [ctypes.c_int]
         _lib = lib
     return _lib
 
@@ -140,6 +141,11 @@ def _field(U: np.ndarray, cfg: dict) -> np.ndarray:
 def threads() -> int:
     """OpenMP threads used by the oracle's loops."""
     return int(_load().ora_threads())
+
+
+def set_threads(n: int) -> None:
+    """Thread count of the oracle's loops for the following calls."""
+    _load().ora_set_threads(int(n))
 
 
 # ----------------------------------------------------------------- per cell

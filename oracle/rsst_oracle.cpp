@@ -416,6 +416,9 @@ int ora_version(void) { return 1; }
 // OpenMP threads the oracle's loops use.
 int ora_threads(void) { return omp_get_max_threads(); }
 
+// Threads for the following calls (timing on one core vs all host cores).
+void ora_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+
 // Primitive recovery of one cell: out = (rho, V1, V2, V3, P, a2, a, |V|, c_tot)
 void ora_prim(int ndim, double gamma, double xi, const double* u, double* out) {
   Prim<double> p = primitives(u, ndim, gamma, xi);

@@ -152,7 +152,10 @@ __host__ __device__ inline Carve carve(int ndim, int ts, int nwx) {
 }
 
 // Rows per 3D tile for a row of nwx waves (512 threads at most).
-__host__ __device__ constexpr int tile_rows(int nwx) { return nwx == 1 ? 8 : (nwx == 2 ? 4 : 2); }
+#ifndef RSST_TS_WIDE
+#define RSST_TS_WIDE 2
+#endif
+__host__ __device__ constexpr int tile_rows(int nwx) { return nwx == 1 ? 8 : (nwx == 2 ? 4 : RSST_TS_WIDE); }
 
 // One stage of R over one tile (3D: TS stacked y rows of one z-chunk) or one
 // group of strips (1D/2D: row r of the workgroup marches chunk
@@ -243,14 +246,18 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
     jj = map_index(j0 + ts_eff + 1, G.ns, A.bc_lo[1], A.bc_hi[1], n); nhi2 = n ? 2 : -1; chi2 = (jj * G.nx + i) * SZ;
     bhi2 = (A.bg_axis == 1) ? jj : bgi_xy;
   }
-  // An edge row of a tile with at least two rows reads the two rows outside
-  // its side one plane ahead, so their load latency hides behind a whole
-  // plane of work; a one-row tile (both sides) loads them when needed.
-  const bool pre = HS && (first_row != last_row);
-  const int oc1 = first_row ? clo1 : chi1, oc2 = first_row ? clo2 : chi2;
-  const int on1 = first_row ? nlo1 : nhi1, on2 = first_row ? nlo2 : nhi2;
-  const int ob1 = first_row ? blo1 : bhi1, ob2 = first_row ? blo2 : bhi2;
-  double o1[NV], o2[NV];
+  // The edge rows read the two rows outside their side of the tile one
+  // plane ahead, so their load latency hides behind a whole plane of work:
+  // o1, o2 hold the near and far outside rows of the wave's side (one-row
+  // tiles, where a row is both edges: o1, o2 below and o3, o4 above).  A
+  // ragged one-row tile of a taller tile shape loads them when needed.
+  constexpr bool ONE = HS && TSC == 1;
+  const bool pre = HS && (ONE || first_row != last_row);
+  const bool o_lo = first_row;  // o1, o2 are the rows below (else above)
+  const int oc1 = o_lo ? clo1 : chi1, oc2 = o_lo ? clo2 : chi2;
+  const int on1 = o_lo ? nlo1 : nhi1, on2 = o_lo ? nlo2 : nhi2;
+  const int ob1 = o_lo ? blo1 : bhi1, ob2 = o_lo ? blo2 : bhi2;
+  double o1[NV], o2[NV], o3[ONE ? NV : 1], o4[ONE ? NV : 1];
 
   double q0[NV], q1[NV], sm0[NV], Fm_lo[NV];
   double cmax = 0.0;
@@ -282,6 +289,10 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
   if (pre) {
     load_cell<NDIM, ST>(A, uin, k0l * plane, oc1, on1, bg_on_m ? k0l : ob1, o1);
     load_cell<NDIM, ST>(A, uin, k0l * plane, oc2, on2, bg_on_m ? k0l : ob2, o2);
+    if constexpr (ONE) {
+      load_cell<NDIM, ST>(A, uin, k0l * plane, chi1, nhi1, bg_on_m ? k0l : bhi1, o3);
+      load_cell<NDIM, ST>(A, uin, k0l * plane, chi2, nhi2, bg_on_m ? k0l : bhi2, o4);
+    }
   }
 
   for (int it = 0; it < G.km; ++it) {
@@ -383,7 +394,7 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
       }
       if (last_row && pre) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) uU[v] = o1[v];
+        for (int v = 0; v < NV; ++v) uU[v] = ONE ? o3[ONE ? v : 0] : o1[v];
       } else if (last_row) {
         load_cell<NDIM, ST>(A, uin, koff, chi1, nhi1, bg_on_m ? k : bhi1, uU);
       } else {
@@ -403,7 +414,7 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
           double u2[NV], hh[NV], Fh[NV];
           if (pre) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) u2[v] = o2[v];
+            for (int v = 0; v < NV; ++v) u2[v] = ONE ? o4[ONE ? v : 0] : o2[v];
           } else {
             load_cell<NDIM, ST>(A, uin, koff, chi2, nhi2, bg_on_m ? k : bhi2, u2);
           }
@@ -440,6 +451,10 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
       const int kn = min(kraw + 1, G.nm - 1);
       load_cell<NDIM, ST>(A, uin, kn * plane, oc1, on1, bg_on_m ? kn : ob1, o1);
       load_cell<NDIM, ST>(A, uin, kn * plane, oc2, on2, bg_on_m ? kn : ob2, o2);
+      if constexpr (ONE) {
+        load_cell<NDIM, ST>(A, uin, kn * plane, chi1, nhi1, bg_on_m ? kn : bhi1, o3);
+        load_cell<NDIM, ST>(A, uin, kn * plane, chi2, nhi2, bg_on_m ? kn : bhi2, o4);
+      }
     }
     __syncthreads();  // B2
 
