@@ -125,6 +125,38 @@ def bench_batch(R, W, np, torch, stream, args):
     return res
 
 
+def bench_convergence(R, W, np, torch, stream):
+    import math
+    res, errs, ms = {}, {}, 0.0
+    for N in (64, 128, 256):
+        cfg, U0, meta = W.wave2d_oblique(N, "pvs")
+        U = torch.from_numpy(U0).cuda()
+        s = R.Solver(cfg, t_end=meta["t_end"])
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        s.steps(U, 40 * N)
+        b.record(stream)
+        b.synchronize()
+        ms += a.elapsed_time(b)
+        t, _ = s.time()
+        s.close()
+        th = meta["theta"]
+
+        def fields(V):
+            rho = V[0]
+            vx, vy = V[1] / rho, V[2] / rho
+            P = (GAMMA - 1) * (V[3] - 0.5 * rho * (vx * vx + vy * vy))
+            return {"S": np.log(P) - GAMMA * np.log(rho), "Vperp": -vx * math.sin(th) + vy * math.cos(th),
+                    "rho": rho, "P": P}
+        f0, f1 = fields(U0), fields(U.cpu().numpy())
+        errs[N] = {k: float(np.mean(np.abs(f1[k] - f0[k]))) for k in f0}
+        res[f"t_reached_{N}"] = t
+    res["L1"] = {str(N): errs[N] for N in errs}
+    res["order_64_256"] = {k: round(0.5 * math.log2(errs[64][k] / errs[256][k]), 3) for k in errs[64]}
+    res["gpu_ms_all_runs"] = round(ms, 2)
+    return res
+
+
 def bench_adjoint(R, W, np, torch, stream, args):
     """Gradient of the final kinetic energy of the 256^2 bubble (xi = 10,
     400 fixed-dt steps, checkpoints every 20) w.r.t. the initial density
@@ -378,6 +410,9 @@ def main():
         sec.update(bench_batch(R, W, np, torch, stream, args))
     if not args.no_adjoint:
         sec.update(bench_adjoint(R, W, np, torch, stream, args))
+    # Sec. 4.2 linear wave at 30 degrees (PVS, xi = 5) to t = 1 at N = 64,
+    # 128, 256: L1 errors against the initial snapshot and their orders
+    sec["wave2d_convergence_pvs"] = bench_convergence(R, W, np, torch, stream)
     out["secondary"] = sec
 
     if not args.no_cpu:

@@ -498,19 +498,8 @@ def test_sound_wave_travels_at_reduced_speed(form, xi):
 # ------------------------------------------------------ convergence (Sec. 4.2)
 
 def _wave30(N, form):
-    th = math.radians(30.0)
-    Lx, Ly = 1 / math.cos(th), 1 / math.sin(th)
-    cfg = W.base_cfg(2, [N, N], xi=5.0, form=form, length=[Lx, Ly])
-    x = W.centres(cfg, 0)[None, :]
-    y = W.centres(cfg, 1)[:, None]
-    xp = x * math.cos(th) + y * math.sin(th)
-    eps = 1e-5
-    rho = 1 + eps * np.sin(2 * math.pi * xp)
-    vperp = eps * np.sin(2 * math.pi * xp)
-    vx = math.cos(th) - vperp * math.sin(th)
-    vy = math.sin(th) + vperp * math.cos(th)
-    P = np.full_like(rho, 1000.0)
-    return cfg, W.conservative(rho, [vx, vy], P), th
+    cfg, U, meta = W.wave2d_oblique(N, form)
+    return cfg, U, meta["theta"]
 
 
 def _l1_errors(N, form):

@@ -216,6 +216,28 @@ def adjoint2d(n=256, xi=10.0, form="pvs", ndir=32):
                     "U_clean": U_clean}
 
 
+# --------------------------------------------------------------- Sec. 4.2
+
+def wave2d_oblique(n, form="pvs", xi=5.0, theta_deg=30.0, eps=1e-5, P0=1000.0):
+    """Linear entropy + shear wave travelling at theta to x (Sec. 4.2): domain
+    [0, 1/cos] x [0, 1/sin] (one wavelength along the wave vector fits both
+    periods), rho = 1 + eps sin(2 pi x_par), V_par = 1,
+    V_perp = eps sin(2 pi x_par), P = P0; after t = 1 the exact solution is
+    the initial state again."""
+    th = math.radians(theta_deg)
+    Lx, Ly = 1 / math.cos(th), 1 / math.sin(th)
+    cfg = base_cfg(2, [n, n], xi=xi, form=form, length=[Lx, Ly])
+    x = centres(cfg, 0)[None, :]
+    y = centres(cfg, 1)[:, None]
+    xp = x * math.cos(th) + y * math.sin(th)
+    rho = 1 + eps * np.sin(2 * math.pi * xp)
+    vperp = eps * np.sin(2 * math.pi * xp)
+    vx = math.cos(th) - vperp * math.sin(th)
+    vy = math.sin(th) + vperp * math.cos(th)
+    P = np.full_like(rho, P0)
+    return cfg, conservative(rho, [vx, vy], P), {"theta": th, "t_end": 1.0}
+
+
 # --------------------------------------------------------------- random
 
 def random_state(ndim, n, *, seed_k=100, xi=3.0, form="pvs", bc_lo=None, bc_hi=None,
