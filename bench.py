@@ -157,6 +157,49 @@ def bench_convergence(R, W, np, torch, stream):
     return res
 
 
+def run_to(s, U, t_end):
+    """CFL steps until t = t_end (the last one cut); returns the step count."""
+    n = 0
+    while True:
+        t, dt = s.time()
+        if t >= t_end:
+            return n
+        if dt > 0 and t + 600 * dt < t_end:
+            s.steps(U, 500)
+            n += 500
+        else:
+            s.step(U)
+            n += 1
+
+
+def bench_rt(R, W, np, torch, stream, n=256):
+    """Sec. 4.4 Rayleigh-Taylor at n^2 to t = 2.5: xi = 1 against the RSST at
+    xi = 6.3 (PVS and PMS): steps, GPU time, max |V_y| and the L1 distance of
+    the density field from the xi = 1 run."""
+    out, ref = {}, None
+    for form, xi in (("pvs", 1.0), ("pvs", 6.3), ("pms", 6.3)):
+        cfg, U0, meta = W.rt2d(n, form=form, xi=xi)
+        U = torch.from_numpy(U0).cuda()
+        s = R.Solver(cfg, t_end=meta["t_end"])
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        steps = run_to(s, U, meta["t_end"])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        s.close()
+        Un = U.cpu().numpy()
+        key = f"{form}_xi{xi:g}"
+        out[key] = {"steps": steps, "wall_s": round(wall, 3), "max_abs_Vy": float(np.abs(Un[2] / Un[0]).max())}
+        if ref is None:
+            ref = Un[0]
+        else:
+            out[key]["L1_rho_vs_xi1"] = float(np.mean(np.abs(Un[0] - ref)))
+            out[key]["step_saving_vs_xi1"] = round(out["pvs_xi1"]["steps"] / steps, 3)
+    out["grid"] = [n, n]
+    out["t_end"] = 2.5
+    return out
+
+
 def bench_adjoint(R, W, np, torch, stream, args):
     """Gradient of the final kinetic energy of the 256^2 bubble (xi = 10,
     400 fixed-dt steps, checkpoints every 20) w.r.t. the initial density
@@ -239,6 +282,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--batch-runs", type=int, default=3)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint workload")
+    ap.add_argument("--no-rt", action="store_true", help="skip the Rayleigh-Taylor workload")
     ap.add_argument("--adjoint-steps", type=int, default=400)
     ap.add_argument("--copy-ref", action="store_true",
                     help="only run a plain device copy of one 256^3 FP64 state (5 x 134 MB), "
@@ -413,6 +457,8 @@ def main():
     # Sec. 4.2 linear wave at 30 degrees (PVS, xi = 5) to t = 1 at N = 64,
     # 128, 256: L1 errors against the initial snapshot and their orders
     sec["wave2d_convergence_pvs"] = bench_convergence(R, W, np, torch, stream)
+    if not args.no_rt:
+        sec["rt2d_256"] = bench_rt(R, W, np, torch, stream)
     out["secondary"] = sec
 
     if not args.no_cpu:

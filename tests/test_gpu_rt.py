@@ -1,0 +1,92 @@
+"""Sec. 4.4 Rayleigh-Taylor problem on the GPU (gravity, closed walls, large
+hydrostatic pressure, the xi-fold longer time step).
+
+Parity: at 64^2 the GPU state after 150 CFL steps matches the oracle's in
+the PVS and PMS forms at xi = 6.3 and at xi = 1 (the bar of the other FP64
+tests, or ten times the oracle's own spread under a last-bit change of the
+input where this run amplifies rounding more).  Step saving: at 128^2 to
+t = 0.5 the RSST run at xi = 6.3 takes at least 4x fewer steps than xi = 1
+(c_tot is dominated by the sound speed, so the ratio approaches xi), and the
+growth of max |V_y| agrees with the xi = 1 run to 10% (the paper's
+statement that the runs evolve alike; its figure values are stripped)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GAMMA = 5.0 / 3.0
+R = None
+
+
+def setup_module(module):
+    global R
+    import paper_1812_04135_amd as lib
+    assert torch.cuda.is_available()
+    lib.lib()
+    R = lib
+
+
+def _scales(Uo):
+    rho = Uo[0]
+    P = (GAMMA - 1) * (Uo[3] - 0.5 * (Uo[1] ** 2 + Uo[2] ** 2) / rho)
+    sm = np.abs(rho).max() * np.sqrt(GAMMA * P / rho).max()
+    return [np.abs(rho).max(), sm, sm, np.abs(Uo[3]).max()]
+
+
+@pytest.mark.parametrize("form,xi", [("pvs", 6.3), ("pms", 6.3), ("pvs", 1.0)])
+def test_rt_matches_oracle(form, xi):
+    cfg, U0, _ = W.rt2d(64, form=form, xi=xi)
+    nsteps = 150
+    U = torch.from_numpy(U0).cuda()
+    s = R.Solver(cfg)
+    s.steps(U, nsteps)
+    tg, _ = s.time()
+    s.close()
+    Ug = U.cpu().numpy()
+    Uo, to, _ = oracle.run(cfg, U0, nsteps)
+    rng = np.random.default_rng(W.seed(81))
+    Up, _, _ = oracle.run(cfg, U0 * (1 + 2.2e-16 * rng.choice([-1.0, 1.0], size=U0.shape)), nsteps)
+    sc = _scales(Uo)
+    err = [float(np.abs(Ug[v] - Uo[v]).max() / sc[v]) for v in range(4)]
+    spread = [float(np.abs(Up[v] - Uo[v]).max() / sc[v]) for v in range(4)]
+    print(f"[rt] {form} xi={xi} err/scale={err} spread={spread} t={tg}/{to}", flush=True)
+    for v in range(4):
+        assert err[v] <= max(1e-12, 10 * spread[v]), (v, err[v], spread[v])
+    assert abs(tg - to) <= 1e-12 * to
+
+
+def run_to(s, U, t_end):
+    """CFL steps until t = t_end (the last one cut); returns the step count.
+    Chunks of 100 while far from t_end, single steps near it."""
+    n = 0
+    while True:
+        t, dt = s.time()
+        if t >= t_end:
+            return n
+        if dt > 0 and t + 120 * dt < t_end:
+            s.steps(U, 100)
+            n += 100
+        else:
+            s.step(U)
+            n += 1
+
+
+def test_rt_step_saving_and_growth():
+    res = {}
+    for xi in (1.0, 6.3):
+        cfg, U0, _ = W.rt2d(128, form="pvs", xi=xi)
+        U = torch.from_numpy(U0).cuda()
+        s = R.Solver(cfg, t_end=0.5)
+        n = run_to(s, U, 0.5)
+        s.close()
+        Un = U.cpu().numpy()
+        res[xi] = (n, float(np.abs(Un[2] / Un[0]).max()))
+    (n1, v1), (n6, v6) = res[1.0], res[6.3]
+    print(f"[rt] 128^2 to t=0.5: xi=1 {n1} steps max|Vy|={v1:.4e}; xi=6.3 {n6} steps max|Vy|={v6:.4e}",
+          flush=True)
+    assert n1 >= 4 * n6
+    assert abs(v6 - v1) <= 0.1 * v1

@@ -238,6 +238,36 @@ def wave2d_oblique(n, form="pvs", xi=5.0, theta_deg=30.0, eps=1e-5, P0=1000.0):
     return cfg, conservative(rho, [vx, vy], P), {"theta": th, "t_end": 1.0}
 
 
+# --------------------------------------------------------------- Sec. 4.4
+
+def _logcosh2(a):
+    """ln(e^a + e^-a), overflow-free."""
+    a = np.abs(a)
+    return a + np.log1p(np.exp(-2.0 * a))
+
+
+def rt_column_mass(y, rho1=1.0, rho2=10.0, L=0.025):
+    """Background column mass from height y to the top (y = 1) of the
+    unperturbed tanh profile, in the closed form of Sec. 4.4."""
+    return (0.5 * (rho1 + rho2) * (1.0 - y)
+            + 0.5 * L * (rho2 - rho1) * (_logcosh2(0.5 / L) - _logcosh2((y - 0.5) / L)))
+
+
+def rt2d(n, form="pvs", xi=6.3, rho1=1.0, rho2=10.0, L=0.025, amp=0.01, Pc=1000.0, gy=-1.0):
+    """Rayleigh-Taylor problem of Sec. 4.4 on [0,1]^2: heavy fluid (rho2) on
+    top of light (rho1) across a tanh layer of width L, density perturbed by
+    (1 + amp sin 4 pi x), hydrostatic P = Pc - m_c g_y with the unperturbed
+    column mass, V = 0, periodic x, closed free-slip walls in y."""
+    cfg = base_cfg(2, [n, n], xi=xi, form=form, bc_lo=["periodic", "reflect"], g=[0.0, gy])
+    x = centres(cfg, 0)[None, :]
+    y = centres(cfg, 1)[:, None]
+    eps = amp * np.sin(4.0 * math.pi * x)
+    rho = (rho1 + 0.5 * (rho2 - rho1) * (1.0 + np.tanh((y - 0.5) / L))) * (1.0 + eps)
+    P = np.broadcast_to(Pc - rt_column_mass(y, rho1, rho2, L) * gy, (n, n)).copy()
+    zero = np.zeros((n, n))
+    return cfg, conservative(rho, [zero, zero], P), {"t_end": 2.5}
+
+
 # --------------------------------------------------------------- random
 
 def random_state(ndim, n, *, seed_k=100, xi=3.0, form="pvs", bc_lo=None, bc_hi=None,
