@@ -408,6 +408,25 @@ def main():
         "effective_GBs": round(5 * nv * 4 * ncell / (ms32 * 1e-3) / 1e9, 1),
         "speedup_vs_fp64": round(ms_step / ms32, 3)}
 
+    # the same 256^3 box with xi from the sound speed (eq. cx), C_max = 0.1
+    # (a runs from 0.18 at the top to 0.84 at the bottom): time per step and
+    # the CFL step it allows against the constant xi = 30
+    cfg_c = dict(cfg, cmax=0.1)
+    Uc = torch.from_numpy(U0).to(dev)
+    sc = R.Solver(cfg_c)
+    msc = timed(sc, Uc, K)
+    sc.prime(torch.from_numpy(U0).to(dev))
+    _, dtc = sc.time()
+    sc.close()
+    s30 = R.Solver(cfg)
+    s30.prime(torch.from_numpy(U0).to(dev))
+    _, dt30 = s30.time()
+    s30.close()
+    sec["strat3d_cmax_fp64"] = {"cmax": 0.1, "ms_per_step": round(msc, 5),
+                                "Gcell_updates_s": round(ncell / (msc * 1e-3) / 1e9, 4),
+                                "speed_vs_constant_xi": round(ms_step / msc, 3),
+                                "cfl_dt": dtc, "cfl_dt_constant_xi30": dt30}
+
     # 2D bubble 512^2 FP64 (L2/MALL resident; launch-latency sensitive)
     cfg2, U2_0, meta2 = W.bubble2d()
     U2 = torch.from_numpy(U2_0).to(dev)
@@ -490,6 +509,15 @@ def main():
         err32 = max(float(np.abs(g32[v] - pert[v]).max() / sc[v]) for v in range(nv))
         s.close()
         out["secondary"]["strat3d_fp32_pert"]["err_vs_oracle_pert"] = err32
+        # C_max mode: one step of the 256^3 box against the oracle
+        Uoc, _, _ = oracle.run(cfg_c, U0, 1)
+        Ugc = torch.from_numpy(U0).to(dev)
+        s = R.Solver(cfg_c)
+        s.step(Ugc)
+        torch.cuda.synchronize()
+        s.close()
+        out["secondary"]["strat3d_cmax_fp64"]["err_vs_oracle"] = parity_err(Ugc.cpu().numpy(), Uoc, 3)
+        out["secondary"]["strat3d_cmax_fp64"]["err_steps"] = 1
         # the bubble's FP32 perturbation over 5 steps against the FP64 oracle
         Uo2, _, _ = oracle.run(cfg2, meta2["bg"][:, :, None] + U2p0.astype(np.float64), 5)
         g2 = torch.from_numpy(U2p0).to(dev)

@@ -79,6 +79,12 @@ typedef struct rsst_config {
   double t_end;      /* > 0: the CFL step is cut so that t never passes t_end;
                         0: no end time                                        */
   int flags;         /* or of rsst_flag                                       */
+  double cmax;       /* > 0: upper limit C_max of the sound speed; xi is then
+                        [1 + (a/C_max)^4]^(1/4) of each state's own sound
+                        speed a (eq. cx): c_tot of every face state and cell,
+                        and f = 1 - 1/xi^2 of every cell's correction.  The
+                        field xi is unused.  0: the constant xi.  Not with
+                        the batch or the adjoint (RSST_E_UNSUPPORTED).        */
 } rsst_config;
 
 enum rsst_flag {

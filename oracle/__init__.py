@@ -48,6 +48,7 @@ class _Config(ctypes.Structure):
         ("bc_lo", ctypes.c_int * 3),
         ("bc_hi", ctypes.c_int * 3),
         ("form", ctypes.c_int),
+        ("cmax", ctypes.c_double),
     ]
 
 
@@ -62,7 +63,7 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         dp = ctypes.POINTER(ctypes.c_double)
         cp = ctypes.POINTER(_Config)
-        lib.ora_prim.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp]
+        lib.ora_prim.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, dp]
         lib.ora_flux.argtypes = [ctypes.c_int, ctypes.c_double, dp, ctypes.c_int, dp]
         lib.ora_flux_jacobian.argtypes = [ctypes.c_int, ctypes.c_double, dp, ctypes.c_int, dp]
         lib.ora_mc.argtypes = [ctypes.c_double, ctypes.c_double]
@@ -70,7 +71,7 @@ def _load():
         lib.ora_llf.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp,
                                 ctypes.c_int, dp]
         lib.ora_llf.restype = ctypes.c_int
-        lib.ora_correct.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
+        lib.ora_correct.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_int, dp, dp, dp, dp]
         lib.ora_cfl_dt.argtypes = [cp, dp]
         lib.ora_cfl_dt.restype = ctypes.c_double
@@ -127,6 +128,7 @@ def make_config(cfg: dict) -> _Config:
     c.dt_rule = int(cfg.get("dt_rule", 0))
     f = cfg.get("form", "pvs")
     c.form = FORMS[f] if isinstance(f, str) else int(f)
+    c.cmax = float(cfg.get("cmax", 0.0))
     return c
 
 
@@ -150,11 +152,11 @@ def set_threads(n: int) -> None:
 
 # ----------------------------------------------------------------- per cell
 
-def prim(u, ndim: int, gamma: float, xi: float = 1.0) -> dict:
+def prim(u, ndim: int, gamma: float, xi: float = 1.0, cmax: float = 0.0) -> dict:
     lib = _load()
     u = _vec(u, ndim + 2)
     out = np.zeros(9)
-    lib.ora_prim(ndim, gamma, xi, _ptr(u), _ptr(out))
+    lib.ora_prim(ndim, gamma, xi, cmax, _ptr(u), _ptr(out))
     return {"rho": out[0], "v": out[1:1 + ndim].copy(), "P": out[4], "a2": out[5],
             "a": out[6], "vabs": out[7], "ctot": out[8]}
 
@@ -188,13 +190,13 @@ def llf(UL, UR, ndim: int, gamma: float, xi: float, d: int) -> np.ndarray:
     return F
 
 
-def correct(u, D, ndim: int, gamma: float, xi: float, form, g=(0.0, 0.0, 0.0)) -> np.ndarray:
+def correct(u, D, ndim: int, gamma: float, xi: float, form, g=(0.0, 0.0, 0.0), cmax: float = 0.0) -> np.ndarray:
     lib = _load()
     u, D = _vec(u, ndim + 2), _vec(D, ndim + 2)
     gg = _vec(list(g) + [0.0] * 3)
     R = np.zeros(ndim + 2)
     fi = FORMS[form] if isinstance(form, str) else int(form)
-    lib.ora_correct(ndim, gamma, xi, fi, _ptr(u), _ptr(D), _ptr(gg), _ptr(R))
+    lib.ora_correct(ndim, gamma, xi, cmax, fi, _ptr(u), _ptr(D), _ptr(gg), _ptr(R))
     return R
 
 

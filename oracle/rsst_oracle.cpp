@@ -65,6 +65,7 @@ typedef struct {
   int bc_lo[3];    // 0 periodic, 1 reflecting (closed free-slip)
   int bc_hi[3];
   int form;        // 0 Euler, 1 PVS, 2 PMS, 3 DVS, 4 DMS, 5 PD
+  double cmax;     // > 0: xi from the upper limit of the sound speed (eq. cx)
 } ora_config;
 
 }  // extern "C"
@@ -128,8 +129,28 @@ struct Prim {
   S rho, v[3], P, a2, a, vabs, ctot;
 };
 
+// The reduction rate: a constant xi (Sec. 4.1), or, with an upper limit
+// C_max of the sound speed, xi = [1 + (a/C_max)^4]^(1/4) evaluated from the
+// local sound speed a of the state at hand (eq. cx, Sec. 4.1 "Functional
+// form of the speed of sound reduction rate").
 template <class S>
-static Prim<S> primitives(const S* u, int ndim, double gamma, const S& xi) {
+struct Xi {
+  S c;          // the constant rate
+  double cmax;  // > 0 selects eq. cx
+};
+
+template <class S>
+static S xi_at(const Xi<S>& x, const S& a) {
+  if (x.cmax > 0.0) {
+    S r = a / x.cmax;
+    S w = 1.0 + (r * r) * (r * r);
+    return ssqrt(ssqrt(w));
+  }
+  return x.c;
+}
+
+template <class S>
+static Prim<S> primitives(const S* u, int ndim, double gamma, const Xi<S>& xi) {
   Prim<S> p;
   p.rho = u[0];
   S mv = S(0.0);  // sum_i m_i V_i = rho |V|^2
@@ -144,7 +165,7 @@ static Prim<S> primitives(const S* u, int ndim, double gamma, const S& xi) {
   p.a2 = gamma * p.P / p.rho;
   p.a = ssqrt(p.a2);
   p.vabs = ssqrt(v2);
-  p.ctot = p.vabs + p.a / xi;
+  p.ctot = p.vabs + p.a / xi_at(xi, p.a);
   return p;
 }
 
@@ -178,7 +199,7 @@ static S mc_slope(const S& l, const S& r) {
 // Returns false if either face state is non-physical.
 template <class S>
 static bool llf_flux(const S* UL, const S* UR, int ndim, int d, double gamma,
-                     const S& xi, S* Fhat) {
+                     const Xi<S>& xi, S* Fhat) {
   const int nv = ndim + 2;
   Prim<S> pl = primitives(UL, ndim, gamma, xi);
   Prim<S> pr = primitives(UR, ndim, gamma, xi);
@@ -205,10 +226,11 @@ static bool llf_flux(const S* UL, const S* UR, int ndim, int d, double gamma,
 // (E + P = e + P + rho V^2/2 and E + P - rho V^2 = e + P - rho V^2/2.)
 template <class S>
 static void rsst_correct(const S* u, const S* D, int ndim, double gamma,
-                         const S& xi, int form, const double* g, S* R) {
+                         const Xi<S>& xi, int form, const double* g, S* R) {
   const int nv = ndim + 2;
   Prim<S> p = primitives(u, ndim, gamma, xi);
-  S f = 1.0 - 1.0 / (xi * xi);
+  const S xc = xi_at(xi, p.a);  // the cell's rate
+  S f = 1.0 - 1.0 / (xc * xc);
   S v2 = S(0.0);
   for (int d = 0; d < ndim; ++d) v2 = v2 + p.v[d] * p.v[d];
   S vdm = S(0.0);
@@ -316,7 +338,7 @@ static void slopes_at(const Grid& G, const ora_config* c, const S* U, const int 
 // along axis d (the face i+1/2).
 template <class S>
 static bool face_flux(const Grid& G, const ora_config* c, const S* U, const int idx[3],
-                      int d, const S& xi, S* Fhat) {
+                      int d, const Xi<S>& xi, S* Fhat) {
   int ir[3] = {idx[0], idx[1], idx[2]};
   ir[d] += 1;
   S sl[5], sr[5], UL[5], UR[5];
@@ -332,7 +354,7 @@ static bool face_flux(const Grid& G, const ora_config* c, const S* U, const int 
 // Full semi-discrete right-hand side R(U) on every cell.
 // Returns the number of non-physical face or cell states met.
 template <class S>
-static int64_t rate_field(const ora_config* c, const S* U, const S& xi, S* R) {
+static int64_t rate_field(const ora_config* c, const S* U, const Xi<S>& xi, S* R) {
   const Grid G = make_grid(c);
   const int nv = G.nv;
   int64_t bad = 0;
@@ -371,7 +393,7 @@ static double max_ctot(const ora_config* c, const double* U) {
   for (int64_t ci = 0; ci < G.ncell; ++ci) {
     double u[5];
     for (int v = 0; v < G.nv; ++v) u[v] = U[(int64_t)v * G.ncell + ci];
-    Prim<double> p = primitives(u, G.ndim, c->gamma, c->xi);
+    Prim<double> p = primitives(u, G.ndim, c->gamma, Xi<double>{c->xi, c->cmax});
     if (p.ctot > cmax) cmax = p.ctot;
   }
   return cmax;
@@ -394,7 +416,7 @@ static double cfl_dt(const ora_config* c, const double* U) {
 // One second-order SSP Runge-Kutta step with a given dt:
 //   U1 = U + dt R(U);   U <- (U + (U1 + dt R(U1))) / 2
 template <class S>
-static int64_t ssp_rk2(const ora_config* c, S* U, const S& xi, double dt) {
+static int64_t ssp_rk2(const ora_config* c, S* U, const Xi<S>& xi, double dt) {
   const Grid G = make_grid(c);
   const int64_t len = (int64_t)G.nv * G.ncell;
   std::vector<S> R(len), U1(len);
@@ -420,14 +442,14 @@ int ora_threads(void) { return omp_get_max_threads(); }
 void ora_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 
 // Primitive recovery of one cell: out = (rho, V1, V2, V3, P, a2, a, |V|, c_tot)
-void ora_prim(int ndim, double gamma, double xi, const double* u, double* out) {
-  Prim<double> p = primitives(u, ndim, gamma, xi);
+void ora_prim(int ndim, double gamma, double xi, double cmax, const double* u, double* out) {
+  Prim<double> p = primitives(u, ndim, gamma, Xi<double>{xi, cmax});
   out[0] = p.rho; out[1] = p.v[0]; out[2] = p.v[1]; out[3] = p.v[2];
   out[4] = p.P; out[5] = p.a2; out[6] = p.a; out[7] = p.vabs; out[8] = p.ctot;
 }
 
 void ora_flux(int ndim, double gamma, const double* u, int d, double* F) {
-  Prim<double> p = primitives(u, ndim, gamma, 1.0);
+  Prim<double> p = primitives(u, ndim, gamma, Xi<double>{1.0, 0.0});
   euler_flux(u, p, ndim, d, F);
 }
 
@@ -436,7 +458,7 @@ void ora_flux_jacobian(int ndim, double gamma, const double* u, int d, double* J
   const int nv = ndim + 2;
   Dual<5> ud[5];
   for (int k = 0; k < nv; ++k) { ud[k] = Dual<5>(u[k]); ud[k].d[k] = 1.0; }
-  Prim<Dual<5>> p = primitives(ud, ndim, gamma, Dual<5>(1.0));
+  Prim<Dual<5>> p = primitives(ud, ndim, gamma, Xi<Dual<5>>{Dual<5>(1.0), 0.0});
   Dual<5> F[5];
   euler_flux(ud, p, ndim, d, F);
   for (int r = 0; r < nv; ++r)
@@ -447,19 +469,19 @@ double ora_mc(double l, double r) { return mc_slope(l, r); }
 
 int ora_llf(int ndim, double gamma, double xi, const double* UL, const double* UR, int d,
             double* F) {
-  return llf_flux(UL, UR, ndim, d, gamma, xi, F) ? 0 : 1;
+  return llf_flux(UL, UR, ndim, d, gamma, Xi<double>{xi, 0.0}, F) ? 0 : 1;
 }
 
-void ora_correct(int ndim, double gamma, double xi, int form, const double* u,
+void ora_correct(int ndim, double gamma, double xi, double cmax, int form, const double* u,
                  const double* D, const double* g, double* R) {
-  rsst_correct(u, D, ndim, gamma, xi, form, g, R);
+  rsst_correct(u, D, ndim, gamma, Xi<double>{xi, cmax}, form, g, R);
 }
 
 double ora_cfl_dt(const ora_config* c, const double* U) { return cfl_dt(c, U); }
 
 // R(U) on the whole grid; returns the count of non-physical states met.
 int64_t ora_rate(const ora_config* c, const double* U, double* R) {
-  return rate_field(c, U, c->xi, R);
+  return rate_field(c, U, Xi<double>{c->xi, c->cmax}, R);
 }
 
 // Advance U by nsteps SSP-RK2 steps.  dt_fixed > 0 uses that dt; otherwise
@@ -476,7 +498,7 @@ int64_t ora_run(const ora_config* c, double* U, int nsteps, double dt_fixed, dou
     if (t_end > 0.0 && t >= t_end) break;
     dt = (dt_fixed > 0.0) ? dt_fixed : cfl_dt(c, U);
     if (t_end > 0.0 && t + dt > t_end) dt = t_end - t;
-    bad += ssp_rk2(c, U, c->xi, dt);
+    bad += ssp_rk2(c, U, Xi<double>{c->xi, c->cmax}, dt);
     t += dt;
   }
   if (t_io) *t_io = t;
@@ -502,7 +524,8 @@ int64_t ora_run_tangent(const ora_config* c, double* U, double* dU, const double
   Dual<N> xi(c->xi);
   for (int k = 0; k < K; ++k) xi.d[k] = dxi[k];
   int64_t bad = 0;
-  for (int s = 0; s < nsteps; ++s) bad += ssp_rk2(c, W.data(), xi, dt);
+  const Xi<Dual<N>> law{xi, c->cmax};
+  for (int s = 0; s < nsteps; ++s) bad += ssp_rk2(c, W.data(), law, dt);
   for (int64_t q = 0; q < len; ++q) {
     U[q] = W[q].v;
     for (int k = 0; k < K; ++k) dU[(int64_t)k * len + q] = W[q].d[k];
@@ -512,7 +535,7 @@ int64_t ora_run_tangent(const ora_config* c, double* U, double* dU, const double
 
 // Diagnostics in FP64, summed in cell order:
 // out = (sum rho, sum m1, sum m2, sum m3, sum E, sum |m|^2/(2 rho), max |V|,
-//        max xi|V|/a), sums multiplied by the cell volume.
+//        max xi|V|/a with the cell's xi), sums multiplied by the cell volume.
 void ora_diag(const ora_config* c, const double* U, double* out) {
   const Grid G = make_grid(c);
   double vol = 1.0;
@@ -521,14 +544,15 @@ void ora_diag(const ora_config* c, const double* U, double* out) {
   for (int64_t ci = 0; ci < G.ncell; ++ci) {
     double u[5];
     for (int v = 0; v < G.nv; ++v) u[v] = U[(int64_t)v * G.ncell + ci];
-    Prim<double> p = primitives(u, G.ndim, c->gamma, c->xi);
+    const Xi<double> law{c->xi, c->cmax};
+    Prim<double> p = primitives(u, G.ndim, c->gamma, law);
     s[0] += u[0];
     double m2 = 0.0;
     for (int d = 0; d < G.ndim; ++d) { s[1 + d] += u[1 + d]; m2 += u[1 + d] * u[1 + d]; }
     s[4] += u[G.nv - 1];
     s[5] += 0.5 * m2 / u[0];
     vmax = std::max(vmax, p.vabs);
-    mmax = std::max(mmax, c->xi * p.vabs / p.a);
+    mmax = std::max(mmax, xi_at(law, p.a) * p.vabs / p.a);
   }
   for (int q = 0; q < 6; ++q) out[q] = s[q] * vol;
   out[6] = vmax;

@@ -42,6 +42,7 @@ class rsst_config(ctypes.Structure):
         ("bg_axis", ctypes.c_int),
         ("t_end", ctypes.c_double),
         ("flags", ctypes.c_int),
+        ("cmax", ctypes.c_double),
     ]
 
 
@@ -143,6 +144,7 @@ def make_config(cfg: dict, prec: str = "fp64", bg=None, bg_axis: int = -1,
     c.bg_axis = int(bg_axis)
     c.t_end = float(t_end)
     c.flags = RSST_WITH_ADJOINT if adjoint else 0
+    c.cmax = float(cfg.get("cmax", 0.0))
     return c
 
 

@@ -14,6 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "librsst.so")
 SOURCES = ["csrc/rsst_kernels.hip", "csrc/rsst_batch.hip", "csrc/rsst_adjoint.hip", "csrc/rsst_api.hip"]
+# the stage kernels, one object per dimension and storage type
+STAGE_UNITS = [(nd, st) for nd in (3, 2, 1) for st in ("double", "float")]
 
 # -packed-fp32-ops off: no packed FP32 instructions anywhere in the library
 HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -21,12 +23,33 @@ HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
 
 
 def build(verbose: bool = False) -> str:
+    """Compile each source to an object in _build/ (in parallel), then link."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    inc = ["-I" + os.path.join(ROOT, "include"), "-I" + os.path.join(HERE, "csrc")]
+    compile_flags = [f for f in HIPFLAGS if f != "-shared"]
+    objs, cmds = [], []
+    for nd, st in STAGE_UNITS:
+        obj = os.path.join(objdir, f"rsst_stage_{nd}d_{st}.o")
+        objs.append(obj)
+        cmds.append(["hipcc"] + compile_flags + inc + [f"-DRSST_INST_NDIM={nd}", f"-DRSST_INST_ST={st}", "-c",
+                                                        os.path.join(HERE, "csrc/rsst_stage_inst.hip"), "-o", obj])
+    for src in SOURCES:
+        obj = os.path.join(objdir, os.path.basename(src).replace(".hip", ".o"))
+        objs.append(obj)
+        cmds.append(["hipcc"] + compile_flags + inc + ["-c", os.path.join(HERE, src), "-o", obj])
+
+    def run(cmd):
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True, cwd=HERE)
+
+    with ThreadPoolExecutor(max_workers=min(len(cmds), max(1, os.cpu_count() or 1))) as ex:
+        list(ex.map(run, cmds))
     tmp = LIB + ".tmp"
-    cmd = (["hipcc"] + HIPFLAGS + ["-I" + os.path.join(ROOT, "include"), "-I" + os.path.join(HERE, "csrc")]
-           + [os.path.join(HERE, s) for s in SOURCES] + ["-o", tmp])
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True, cwd=HERE)
+    run(["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp])
     os.replace(tmp, LIB)
     return LIB
 

@@ -63,6 +63,8 @@ static int validate(const rsst_config* c) {
   }
   if (!(c->t_end >= 0.0) || !std::isfinite(c->t_end)) return RSST_E_ARG;
   if (c->flags & ~RSST_WITH_ADJOINT) return RSST_E_ARG;
+  if (!(c->cmax >= 0.0) || !std::isfinite(c->cmax)) return RSST_E_ARG;
+  if ((c->flags & RSST_WITH_ADJOINT) && c->cmax > 0.0) return RSST_E_UNSUPPORTED;
   if ((c->flags & RSST_WITH_ADJOINT) && c->prec != RSST_FP64) return RSST_E_UNSUPPORTED;
   // fields are addressed with 32-bit byte offsets
   {
@@ -125,6 +127,7 @@ int rsst_init(const rsst_config* cfg, void* stream, rsst_handle* out) {
   a.inv_gm1 = 1.0 / (cfg->gamma - 1.0);
   a.inv_xi = 1.0 / cfg->xi;
   a.f = 1.0 - 1.0 / (cfg->xi * cfg->xi);
+  a.inv_cmax2 = cfg->cmax > 0.0 ? 1.0 / (cfg->cmax * cfg->cmax) : 0.0;
   a.form = cfg->form;
   double hlen;
   if (cfg->dt_rule == 1) {

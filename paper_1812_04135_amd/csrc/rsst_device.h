@@ -27,6 +27,7 @@ struct Consts {
   double inv_gm1; // 1 / (gamma - 1) = (de/dP)_rho of the ideal gas
   double inv_xi;  // 1 / xi
   double f;       // 1 - 1/xi^2
+  double inv_cmax2;  // 1/C_max^2 when xi follows the sound speed (eq. cx), else 0
 };
 
 // A reconstructed face state: conservative values plus the primitive
@@ -72,9 +73,36 @@ __device__ __forceinline__ double mc_half(double l, double r) {
   return s * h;
 }
 
+// 1/sqrt(x), x >= 1: hardware seed refined by two Newton steps.
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx, y * y, 1.5);
+  return y * fma(-hx, y * y, 1.5);
+}
+
+// With an upper limit C_max of the sound speed (eq. cx) the rate is
+// xi = w^(1/4), w = 1 + (a/C_max)^4, taken from the sound speed of the state
+// at hand.  Effective sound speed a/xi = a w^(-1/4), from a^2:
+__device__ __forceinline__ double a_eff_cmax(double a2, const Consts& K) {
+  const double r2 = a2 * K.inv_cmax2;
+  const double y = rsq_nr(fma(r2, r2, 1.0));  // w^(-1/2)
+  return sqrt_nr(a2) * sqrt_nr(y);
+}
+
+// f = 1 - 1/xi^2 = 1 - w^(-1/2) = r^4 y^2 / (1 + y), y = w^(-1/2): no
+// cancellation when a << C_max.
+__device__ __forceinline__ double f_cmax(double a2, const Consts& K) {
+  const double r2 = a2 * K.inv_cmax2;
+  const double r4 = r2 * r2;
+  const double y = rsq_nr(1.0 + r4);
+  return r4 * (y * y) * rcp(1.0 + y);
+}
+
 // Primitive recovery of a face state, normal axis D (Sec. 3.2 and 4.1):
-// V = m/rho, P = (gamma-1)(E - rho|V|^2/2), c_tot = |V| + sqrt(gamma P/rho)/xi.
-template <int NDIM, int D>
+// V = m/rho, P = (gamma-1)(E - rho|V|^2/2), c_tot = |V| + sqrt(gamma P/rho)/xi
+// (XCM: xi from eq. cx).
+template <int NDIM, int D, bool XCM = false>
 __device__ __forceinline__ void face_prims(Face<NDIM + 2>& s, const Consts& K) {
   constexpr int NV = NDIM + 2;
   const double ri = rcp(s.u[0]);
@@ -86,17 +114,18 @@ __device__ __forceinline__ void face_prims(Face<NDIM + 2>& s, const Consts& K) {
     if (e == D) vn = ve;
   }
   s.P = K.gm1 * fma(-0.5 * s.u[0], v2, s.u[NV - 1]);
-  s.c = fma(sqrt_nr(K.gamma * s.P * ri), K.inv_xi, sqrt_nr(v2));
+  if constexpr (XCM) s.c = sqrt_nr(v2) + a_eff_cmax(K.gamma * s.P * ri, K);
+  else s.c = fma(sqrt_nr(K.gamma * s.P * ri), K.inv_xi, sqrt_nr(v2));
   s.vn = vn;
 }
 
 // Face state U + h (h: half slopes, signed) and its primitives.
-template <int NDIM, int D>
+template <int NDIM, int D, bool XCM = false>
 __device__ __forceinline__ void make_face(const double (&u)[NDIM + 2], const double (&h)[NDIM + 2],
                                           bool plus, const Consts& K, Face<NDIM + 2>& s) {
 #pragma unroll
   for (int v = 0; v < NDIM + 2; ++v) s.u[v] = plus ? u[v] + h[v] : u[v] - h[v];
-  face_prims<NDIM, D>(s, K);
+  face_prims<NDIM, D, XCM>(s, K);
 }
 
 // Twice the local Lax-Friedrichs flux between left state L and right state
@@ -132,8 +161,8 @@ __device__ __forceinline__ Face<NDIM + 2> mirror(const Face<NDIM + 2>& s) {
 // Corrected time derivative of one cell (eq. pvs_dt, pvs_dt_dpr; App. A.1-A.4)
 // plus the external force (App. B).  u: stage-input cell state; Dl: the
 // uncorrected increments (Delta rho, Delta m_i, Delta E).  Returns the
-// non-physical flags of the cell.
-template <int NDIM, int FORM>
+// non-physical flags of the cell.  XCM: f from the cell's own xi (eq. cx).
+template <int NDIM, int FORM, bool XCM = false>
 __device__ __forceinline__ unsigned rsst_rate(const double (&u)[NDIM + 2], const double (&Dl)[NDIM + 2],
                                               const Consts& K, const double (&g)[3],
                                               double (&R)[NDIM + 2]) {
@@ -156,12 +185,13 @@ __device__ __forceinline__ unsigned rsst_rate(const double (&u)[NDIM + 2], const
 #pragma unroll
   for (int q = 0; q < NV; ++q) R[q] = Dl[q];
   if constexpr (FORM != kEuler) {
+    const double f = XCM ? f_cmax(K.gamma * P * ri, K) : K.f;
     // Delta P = (gamma-1) (|V|^2/2 Delta rho - V.Delta m + Delta E)
     const double dP = K.gm1 * (fma(0.5 * v2, Dl[0], Dl[NV - 1]) - vdm);
     const double H = (u[NV - 1] + P) * ri;  // (E + P)/rho
     if constexpr (FORM == kPVS || FORM == kPMS) {
       // s = f Delta P / a^2, a^2 = gamma P / rho
-      const double s = K.f * dP * rho * rcp(K.gamma * P);
+      const double s = f * dP * rho * rcp(K.gamma * P);
       R[0] -= s;
       if constexpr (FORM == kPVS) {
 #pragma unroll
@@ -171,7 +201,7 @@ __device__ __forceinline__ unsigned rsst_rate(const double (&u)[NDIM + 2], const
         R[NV - 1] = fma(-(H - v2), s, R[NV - 1]);
       }
     } else if constexpr (FORM == kDVS || FORM == kDMS) {
-      const double s = K.f * Dl[0];
+      const double s = f * Dl[0];
       R[0] -= s;
       if constexpr (FORM == kDVS) {
 #pragma unroll
@@ -181,7 +211,7 @@ __device__ __forceinline__ unsigned rsst_rate(const double (&u)[NDIM + 2], const
         R[NV - 1] = fma(-(H - v2), s, R[NV - 1]);
       }
     } else {  // PD: energy only, (de/dP)_rho Delta P
-      R[NV - 1] = fma(-K.f * K.inv_gm1, dP, R[NV - 1]);
+      R[NV - 1] = fma(-f * K.inv_gm1, dP, R[NV - 1]);
     }
   }
 #pragma unroll
@@ -193,7 +223,7 @@ __device__ __forceinline__ unsigned rsst_rate(const double (&u)[NDIM + 2], const
 }
 
 // c_tot of a cell state (for the CFL time step).
-template <int NDIM>
+template <int NDIM, bool XCM = false>
 __device__ __forceinline__ double cell_ctot(const double (&u)[NDIM + 2], const Consts& K) {
   constexpr int NV = NDIM + 2;
   const double ri = rcp(u[0]);
@@ -204,7 +234,8 @@ __device__ __forceinline__ double cell_ctot(const double (&u)[NDIM + 2], const C
     v2 = fma(ve, ve, v2);
   }
   const double P = K.gm1 * fma(-0.5 * u[0], v2, u[NV - 1]);
-  return fma(sqrt_nr(K.gamma * P * ri), K.inv_xi, sqrt_nr(v2));
+  if constexpr (XCM) return sqrt_nr(v2) + a_eff_cmax(K.gamma * P * ri, K);
+  else return fma(sqrt_nr(K.gamma * P * ri), K.inv_xi, sqrt_nr(v2));
 }
 
 // ---- cross-lane moves (wave64 DPP) -------------------------------------

@@ -29,6 +29,7 @@ struct StageArgs {
   int bc_lo[3], bc_hi[3];  // physical axes
   double inv_dx[3];
   double gamma, gm1, inv_gm1, inv_xi, f;
+  double inv_cmax2;  // > 0: xi = [1 + (a/C_max)^4]^(1/4) per state (eq. cx)
   double g[3];
   int form;
   double dt_fixed;   // > 0: use it, else scal[kDtCur]
@@ -48,6 +49,9 @@ struct StageArgs {
 Geometry plan_geometry(int ndim, const int n[3]);
 
 hipError_t launch_stage(const StageArgs& a, int stage, hipStream_t s);
+// One instantiation per (NDIM, ST) lives in its own object (rsst_stage_inst.hip).
+template <int NDIM, typename ST>
+hipError_t launch_stage_n(const StageArgs& a, int stage, hipStream_t s);
 hipError_t launch_prime(const StageArgs& a, const void* u, double t0, int set_t, hipStream_t s);
 hipError_t launch_diag(const StageArgs& a, const void* u, double* partial, int npartial,
                        double* out8, hipStream_t s);

@@ -1,4 +1,5 @@
-// Fused RSST stage kernels for gfx950.
+// Fused RSST stage kernels for gfx950 (the kernels themselves are
+// instantiated per dimension and storage type in rsst_stage_inst.hip).
 //
 // One launch computes one SSP-RK2 stage (Sec. 4.1, items 2-8) for the whole
 // grid in a single pass over HBM:
@@ -33,23 +34,6 @@
 
 namespace rsstk {
 
-template <int NDIM, int STAGE, typename ST, int FORM, int NWXC>
-__global__ void __launch_bounds__(NDIM == 3 ? 512 : 1024) stage_kernel(const StageArgs A) {
-  extern __shared__ double lds[];
-  const Geometry& G = A.geo;
-  const int L = xcd_tile(blockIdx.x, gridDim.x);
-  const int tile_s = L % G.ntile_s;
-  const int chunk_base = (L / G.ntile_s) * (NDIM == 3 ? 1 : G.ts);
-  const double dt = (A.dt_fixed > 0.0) ? A.dt_fixed : A.scal[kDtCur];
-  unsigned bad = 0;
-  const double cmax = stage_body<NDIM, STAGE, ST, FORM, NWXC>(A, lds, tile_s, chunk_base, dt, bad);
-  if (bad) atomicOr((unsigned*)(A.scal + kFlags), bad);
-  if constexpr (STAGE == 2) {
-    const Carve C = carve(NDIM, NDIM == 3 ? tile_rows(NWXC) : G.ts, NDIM == 3 ? NWXC : G.nwx);
-    cfl_epilogue(A, lds + C.red, cmax, dt);
-  }
-}
-
 // ---------------------------------------------------------------- prime
 
 // CFL time step of a state: dt = cfl * h / max c_tot; also sets t = t0.
@@ -57,7 +41,7 @@ template <int NDIM, typename ST>
 __global__ void __launch_bounds__(256) prime_kernel(const StageArgs A, const ST* __restrict__ u,
                                                     double t0, int set_t) {
   constexpr int NV = NDIM + 2;
-  const Consts K{A.gamma, A.gm1, A.inv_gm1, A.inv_xi, A.f};
+  const Consts K{A.gamma, A.gm1, A.inv_gm1, A.inv_xi, A.f, A.inv_cmax2};
   const Geometry& G = A.geo;
   __shared__ double red[4];
   double cm = 0.0;
@@ -79,7 +63,7 @@ __global__ void __launch_bounds__(256) prime_kernel(const StageArgs A, const ST*
 #pragma unroll
       for (int v = 0; v < NV; ++v) q[v] += A.bg[v * A.nbg + b];
     }
-    const double ct = cell_ctot<NDIM>(q, K);
+    const double ct = A.inv_cmax2 > 0.0 ? cell_ctot<NDIM, true>(q, K) : cell_ctot<NDIM>(q, K);
     if (!(q[0] > 0.0)) bad |= kBadRho;
     if (!(ct < INFINITY)) bad |= kNonFinite;
     cm = fmax(cm, ct);
@@ -120,7 +104,7 @@ __global__ void __launch_bounds__(kDiagThreads) diag_partial_kernel(const StageA
                                                                     const ST* __restrict__ u,
                                                                     double* __restrict__ part) {
   constexpr int NV = NDIM + 2;
-  const Consts K{A.gamma, A.gm1, A.inv_gm1, A.inv_xi, A.f};
+  const Consts K{A.gamma, A.gm1, A.inv_gm1, A.inv_xi, A.f, A.inv_cmax2};
   const Geometry& G = A.geo;
   __shared__ double s[8][kDiagThreads];
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -154,9 +138,10 @@ __global__ void __launch_bounds__(kDiagThreads) diag_partial_kernel(const StageA
     mv = m2 * rinv;
     const double v = sqrt(m2) * rinv;
     const double P = K.gm1 * (q[NV - 1] - 0.5 * mv);
-    const double a = sqrt(K.gamma * P * rinv);
+    const double a2 = K.gamma * P * rinv;
+    const double ae = A.inv_cmax2 > 0.0 ? a_eff_cmax(a2, K) : sqrt(a2) * A.inv_xi;  // a / xi
     acc[6] = fmax(acc[6], v);
-    acc[7] = fmax(acc[7], v / (a * A.inv_xi));
+    acc[7] = fmax(acc[7], v / ae);
   }
 #pragma unroll
   for (int q = 0; q < 8; ++q) s[q][threadIdx.x] = acc[q];
@@ -232,49 +217,6 @@ Geometry plan_geometry(int ndim, const int n[3]) {
   G.threads = 64 * G.nwx * G.ts;
   G.lds_bytes = (size_t)carve(ndim, G.ts, G.nwx).total * sizeof(double);
   return G;
-}
-
-template <int NDIM, int STAGE, typename ST, int FORM, int NWXC>
-static hipError_t launch_stage_k(const StageArgs& a, hipStream_t s) {
-  const Geometry& G = a.geo;
-  const dim3 grid((unsigned)(G.ntile_s * G.nchunk)), block((unsigned)G.threads);
-  auto kern = stage_kernel<NDIM, STAGE, ST, FORM, NWXC>;
-  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)G.lds_bytes);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, grid, block, G.lds_bytes, s, a);
-  return hipGetLastError();
-}
-
-template <int NDIM, int STAGE, typename ST, int FORM>
-static hipError_t launch_stage_t(const StageArgs& a, hipStream_t s) {
-  if constexpr (NDIM == 3) {
-    switch (a.geo.nwx) {
-      case 1: return launch_stage_k<NDIM, STAGE, ST, FORM, 1>(a, s);
-      case 2: return launch_stage_k<NDIM, STAGE, ST, FORM, 2>(a, s);
-      case 3: return launch_stage_k<NDIM, STAGE, ST, FORM, 3>(a, s);
-      default: return launch_stage_k<NDIM, STAGE, ST, FORM, 4>(a, s);
-    }
-  } else {
-    return launch_stage_k<NDIM, STAGE, ST, FORM, 0>(a, s);
-  }
-}
-
-template <int NDIM, int STAGE, typename ST>
-static hipError_t launch_stage_f(const StageArgs& a, hipStream_t s) {
-  switch (a.form) {
-    case kEuler: return launch_stage_t<NDIM, STAGE, ST, kEuler>(a, s);
-    case kPVS: return launch_stage_t<NDIM, STAGE, ST, kPVS>(a, s);
-    case kPMS: return launch_stage_t<NDIM, STAGE, ST, kPMS>(a, s);
-    case kDVS: return launch_stage_t<NDIM, STAGE, ST, kDVS>(a, s);
-    case kDMS: return launch_stage_t<NDIM, STAGE, ST, kDMS>(a, s);
-    default: return launch_stage_t<NDIM, STAGE, ST, kPD>(a, s);
-  }
-}
-
-template <int NDIM, typename ST>
-static hipError_t launch_stage_n(const StageArgs& a, int stage, hipStream_t s) {
-  return stage == 1 ? launch_stage_f<NDIM, 1, ST>(a, s) : launch_stage_f<NDIM, 2, ST>(a, s);
 }
 
 template <typename ST>

@@ -165,9 +165,11 @@ __host__ __device__ constexpr int tile_rows(int nwx) { return nwx == 1 ? 8 : (nw
 // NWXC = 0: 1D/2D, nwx and the number of row groups from the geometry.
 // Every row of the workgroup runs the same number of march iterations
 // (G.km), so rows of different chunks share the workgroup's barriers.
-template <int NDIM, int STAGE, typename ST, int FORM, int NWXC>
+template <int NDIM, int STAGE, typename ST, int FORMX, int NWXC>
 __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, int tile_s,
                                              int chunk_base, double dt, unsigned& bad) {
+  constexpr int FORM = FORMX & 7;     // correction form
+  constexpr bool XCM = (FORMX & 8) != 0;  // xi from the sound speed (eq. cx)
   constexpr int NV = NDIM + 2;
   constexpr int PL = NV + 3;          // face payload: U, P, c_tot, V_normal
   constexpr bool HS = (NDIM == 3);    // stacked y rows
@@ -223,7 +225,7 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
   const bool bg_on_m = (sizeof(ST) == 4) && (A.bg_axis == am) && HM;
   auto bgk = [&](int kk) { return bg_on_m ? kk : bgi_xy; };
 
-  const Consts K{A.gamma, A.gm1, A.inv_gm1, A.inv_xi, A.f};
+  const Consts K{A.gamma, A.gm1, A.inv_gm1, A.inv_xi, A.f, A.inv_cmax2};
   const double g[3] = {A.g[0], A.g[1], A.g[2]};
   const double hx = 0.5 * A.inv_dx[0], hy = 0.5 * A.inv_dx[1], hz = 0.5 * A.inv_dx[DM];
   const __amdgpu_buffer_rsrc_t uin = field_rsrc(A.uin, fbytes);
@@ -280,8 +282,8 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
       sm0[v] = mc_half(q0[v] - qb[v], q1[v] - q0[v]);
     }
     Face<NV> fl, fr;
-    make_face<NDIM, DM>(qb, ha, true, K, fl);
-    make_face<NDIM, DM>(q0, sm0, false, K, fr);
+    make_face<NDIM, DM, XCM>(qb, ha, true, K, fl);
+    make_face<NDIM, DM, XCM>(q0, sm0, false, K, fr);
     flux2<NDIM, DM>(fl, fr, Fm_lo);
   } else {
     load_cell<NDIM, ST>(A, uin, 0, col, -1, bgi_xy, q0);
@@ -369,8 +371,8 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
 #pragma unroll
       for (int v = 0; v < NV; ++v) h[v] = mc_half(q0[v] - uL[v], uR[v] - q0[v]);
       Face<NV> fm, fp;
-      make_face<NDIM, 0>(q0, h, false, K, fm);
-      make_face<NDIM, 0>(q0, h, true, K, fp);
+      make_face<NDIM, 0, XCM>(q0, h, false, K, fm);
+      make_face<NDIM, 0, XCM>(q0, h, true, K, fp);
       // the wave-edge faces are redone after the barrier from the seams
       if (!wave_idle) {
         if (lane == 0) put_face(seamM + (row * nwx + wx) * PL, 1, fm);
@@ -406,7 +408,7 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
       for (int v = 0; v < NV; ++v) h[v] = mc_half(q0[v] - uD[v], uU[v] - q0[v]);
       {
         Face<NV> fyp;
-        make_face<NDIM, 1>(q0, h, true, K, fyp);
+        make_face<NDIM, 1, XCM>(q0, h, true, K, fyp);
         put_face(Prow + row * nxp + i_raw, TS * nxp, fyp);
         if (last_row) {
           // minus state of the row above the tile, and the flux at the
@@ -421,13 +423,13 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
 #pragma unroll
           for (int v = 0; v < NV; ++v) hh[v] = mc_half(uU[v] - q0[v], u2[v] - uU[v]);
           Face<NV> fh;
-          make_face<NDIM, 1>(uU, hh, false, K, fh);
+          make_face<NDIM, 1, XCM>(uU, hh, false, K, fh);
           flux2<NDIM, 1>(fyp, fh, Fh);
 #pragma unroll
           for (int v = 0; v < NV; ++v) Frow[(v * (TS + 1) + ts_eff) * nxp + i_raw] = Fh[v];
         }
       }
-      make_face<NDIM, 1>(q0, h, false, K, fym);
+      make_face<NDIM, 1, XCM>(q0, h, false, K, fym);
       if (first_row) {
         // plus state of the row below the tile, and the flux at the tile's
         // lower face
@@ -441,7 +443,7 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
 #pragma unroll
         for (int v = 0; v < NV; ++v) hh[v] = mc_half(uD[v] - u2[v], q0[v] - uD[v]);
         Face<NV> fh;
-        make_face<NDIM, 1>(uD, hh, true, K, fh);
+        make_face<NDIM, 1, XCM>(uD, hh, true, K, fh);
         flux2<NDIM, 1>(fh, fym, Fh);
 #pragma unroll
         for (int v = 0; v < NV; ++v) Frow[(v * (TS + 1)) * nxp + i_raw] = Fh[v];
@@ -526,8 +528,8 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
 #pragma unroll
       for (int v = 0; v < NV; ++v) sm1[v] = mc_half(q1[v] - q0[v], q2[v] - q1[v]);
       Face<NV> fl, fr;
-      make_face<NDIM, DM>(q0, sm0, true, K, fl);
-      make_face<NDIM, DM>(q1, sm1, false, K, fr);
+      make_face<NDIM, DM, XCM>(q0, sm0, true, K, fl);
+      make_face<NDIM, DM, XCM>(q1, sm1, false, K, fr);
       flux2<NDIM, DM>(fl, fr, Fm_hi);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
@@ -537,7 +539,7 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
       }
     }
     double R[NV];
-    const unsigned b = rsst_rate<NDIM, FORM>(q0, Dl, K, g, R);
+    const unsigned b = rsst_rate<NDIM, FORM, XCM>(q0, Dl, K, g, R);
     if (active && kval) {
       bad |= b;
       const int bk = bgk(k);
@@ -553,7 +555,7 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
         buf_store<ST>(uout, col, koff + v * vstride, st);
         out[v] = (double)st + bgv;
       }
-      if constexpr (STAGE == 2) cmax = fmax(cmax, cell_ctot<NDIM>(out, K));
+      if constexpr (STAGE == 2) cmax = fmax(cmax, cell_ctot<NDIM, XCM>(out, K));
     }
     if constexpr (HM) {
 #pragma unroll

@@ -258,3 +258,57 @@ def test_nonphysical_state_is_latched_and_polled():
     assert e.value.code == -5
     assert sol.poll() == 0  # cleared
     sol.close()
+
+
+# xi from the sound speed (eq. cx): C_max near the median sound speed, so
+# xi varies from ~1 to ~2 across each state; every dimension, every form, a
+# 256-wide 3D row, walls and gravity.
+CMAX_CASES = [
+    (1, [90], ["reflect"], [-0.3], "pvs"),
+    (1, [64], ["periodic"], None, "pd"),
+    (2, [70, 33], ["periodic", "reflect"], [0.0, -0.5], "pvs"),
+    (2, [37, 20], ["reflect", "periodic"], [0.2, 0.0], "pms"),
+    (2, [64, 16], ["periodic", "periodic"], None, "dvs"),
+    (2, [33, 18], ["reflect", "reflect"], [0.1, -0.4], "dms"),
+    (2, [20, 33], ["periodic", "reflect"], [0.0, -1.0], "pd"),
+    (3, [37, 9, 8], ["periodic", "periodic", "reflect"], [0.0, 0.0, -1.0], "pvs"),
+    (3, [256, 4, 5], ["periodic", "reflect", "reflect"], [0.0, 0.3, -0.6], "pms"),
+]
+
+
+@pytest.mark.parametrize("ndim,n,bc,g,form", CMAX_CASES,
+                         ids=[f"{c[0]}d-{'x'.join(map(str, c[1]))}-{c[4]}" for c in CMAX_CASES])
+def test_cmax_step_matches_oracle(ndim, n, bc, g, form):
+    cfg, U0 = W.random_state(ndim, n, seed_k=260 + sum(n), xi=4.0, form=form, bc_lo=bc, g=g, mach=0.3)
+    rho = U0[0]
+    m2 = sum(U0[1 + d] ** 2 for d in range(ndim))
+    a = np.sqrt(GAMMA * (GAMMA - 1) * (U0[-1] - 0.5 * m2 / rho) / rho)
+    cfg["cmax"] = float(np.median(a))
+    nsteps = 6
+    Ug, tg, dtg, flags = gpu_run(cfg, U0, nsteps)
+    Uo, to, dto = oracle.run(cfg, U0, nsteps)
+    assert flags == 0
+    assert abs(tg - to) <= 1e-13 * to
+    assert_parity(Ug, Uo, ndim, what=f"cmax {ndim}D {n} {form}")
+    # the mode is live: the run differs from the constant-xi run
+    Uc, _, _, _ = gpu_run(dict(cfg, cmax=0.0), U0, nsteps)
+    assert np.abs(Uc - Ug).max() > 1e-8
+
+
+def test_cmax_fp32_perturbation_and_diag():
+    cfg, U0, meta = W.strat3d(n=32, xi=30.0, nz=24, ny=8)
+    cfg["cmax"] = 0.25  # below the sound speed of the lower half of the box
+    nsteps = 4
+    bg = meta["bg"]
+    U1 = (U0 - bg[:, :, None, None]).astype(np.float32)
+    Ug, _, _, _ = gpu_run(cfg, U1, nsteps, prec="fp32_pert", bg=bg, bg_axis=2)
+    Uo, _, _ = oracle.run(cfg, bg[:, :, None, None] + U1.astype(np.float64), nsteps)
+    err = pert_errors(Ug, Uo, bg[:, :, None, None], 3)
+    print(f"[parity] cmax fp32 err/pert = {err}", flush=True)
+    assert max(err) <= 1e-5
+    U = torch.from_numpy(U0).cuda()
+    s = R.Solver(cfg)
+    d = s.diag(U)
+    s.close()
+    do = oracle.diag(cfg, U0)
+    assert abs(d[7] - do[7]) <= 1e-13 * do[7]

@@ -198,6 +198,80 @@ def test_characteristic_speeds_match_paper(form, ndim):
                 np.testing.assert_allclose(ev, ref, rtol=0, atol=1e-6 * a)
 
 
+# ------------------------------------------ xi from the sound speed (eq. cx)
+
+def test_cmax_effective_sound_speed_limits():
+    """Eq. cx: a/xi stays below both a and C_max, tends to a where a << C_max
+    and to C_max where a >> C_max (the paper's stated purpose), and grows
+    with a."""
+    C = 3.0
+    prev = 0.0
+    for ratio in np.geomspace(1e-3, 1e3, 61):
+        a = ratio * C
+        rho = 1.3
+        P = a * a * rho / GAMMA
+        V = np.array([0.2, -0.1])
+        u = np.array([rho, *(rho * V), P / (GAMMA - 1) + 0.5 * rho * float(V @ V)])
+        p = oracle.prim(u, 2, GAMMA, xi=17.0, cmax=C)
+        ae = p["ctot"] - p["vabs"]
+        assert ae < min(p["a"], C) * (1 + 1e-15)
+        assert ae > prev
+        prev = ae
+        if ratio <= 1e-3:
+            assert abs(ae / p["a"] - 1) <= 1e-12
+        if ratio >= 1e3:
+            assert abs(ae / C - 1) <= 1e-12
+
+
+def test_cmax_diagnostics_effective_mach():
+    """With xi from eq. cx the effective Mach number is |V| over the
+    effective sound speed a/xi(a) (pinned above), for a uniform state."""
+    n = [6, 5]
+    cfg = W.base_cfg(2, n, xi=9.0)
+    cfg["cmax"] = 0.7
+    rho, P, V = 1.4, 2.0, np.array([0.3, -0.2])
+    shape = tuple(reversed(n))
+    U = W.conservative(np.full(shape, rho), [np.full(shape, v) for v in V], np.full(shape, P))
+    out = oracle.diag(cfg, U)
+    p = oracle.prim(U[:, 0, 0], 2, GAMMA, xi=9.0, cmax=0.7)
+    assert abs(out[7] - p["vabs"] / (p["ctot"] - p["vabs"])) <= 1e-14 * out[7]
+
+
+def test_cmax_huge_reduces_to_euler_bitwise():
+    """With C_max far above every sound speed, xi = 1 in every cell and face:
+    the RSST forms are the Euler equations bit for bit (Sec. 3.2), whatever
+    the constant xi field says."""
+    for form in FORMS:
+        cfg, U = W.random_state(2, [12, 10], seed_k=30, xi=7.0, form=form,
+                                bc_lo=["periodic", "reflect"], g=[0.0, -0.3])
+        ce = dict(cfg, form="euler", xi=1.0)
+        cc = dict(cfg, cmax=1e150)
+        assert np.array_equal(oracle.rate(cc, U), oracle.rate(ce, U)), form
+        dt = 0.5 * oracle.cfl_dt(ce, U)
+        assert np.array_equal(oracle.run(cc, U, 3, dt_fixed=dt)[0], oracle.run(ce, U, 3, dt_fixed=dt)[0])
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_cmax_characteristic_speeds(form):
+    """About a uniform state the cell's xi is xi(a0) of eq. cx, so the system
+    propagates at the paper's speeds with that xi: sound at a0/xi(a0)
+    (Sec. 4.1, functional form of the reduction rate)."""
+    rng = np.random.default_rng(7)
+    ndim = 2
+    for ratio in (0.3, 1.0, 4.0):
+        for _ in range(5):
+            u, rho, V, P, a = rand_cell(rng, ndim, mach=0.3)
+            C = a / ratio
+            xi_a = (1.0 + ratio ** 4) ** 0.25
+            M = np.stack([oracle.correct(u, np.eye(ndim + 2)[k], ndim, GAMMA, 1.0, form, cmax=C)
+                          for k in range(ndim + 2)], axis=1)
+            for d in range(ndim):
+                A = oracle.flux_jacobian(u, ndim, GAMMA, d)
+                ref = paper_speeds(form, V[d], a, xi_a, ndim)
+                ev = np.sort(np.linalg.eigvals(M @ A).real)
+                np.testing.assert_allclose(ev, ref, rtol=0, atol=1e-6 * a)
+
+
 @pytest.mark.parametrize("ndim", [1, 2, 3])
 def test_tendency_identities(ndim):
     """Per-form tendencies derived from the paper's primitive forms:
