@@ -283,6 +283,7 @@ def main():
     ap.add_argument("--batch-runs", type=int, default=3)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint workload")
     ap.add_argument("--no-rt", action="store_true", help="skip the Rayleigh-Taylor workload")
+    ap.add_argument("--no-conv", action="store_true", help="skip the linear-wave convergence runs")
     ap.add_argument("--adjoint-steps", type=int, default=400)
     ap.add_argument("--copy-ref", action="store_true",
                     help="only run a plain device copy of one 256^3 FP64 state (5 x 134 MB), "
@@ -475,7 +476,8 @@ def main():
         sec.update(bench_adjoint(R, W, np, torch, stream, args))
     # Sec. 4.2 linear wave at 30 degrees (PVS, xi = 5) to t = 1 at N = 64,
     # 128, 256: L1 errors against the initial snapshot and their orders
-    sec["wave2d_convergence_pvs"] = bench_convergence(R, W, np, torch, stream)
+    if not args.no_conv:
+        sec["wave2d_convergence_pvs"] = bench_convergence(R, W, np, torch, stream)
     if not args.no_rt:
         sec["rt2d_256"] = bench_rt(R, W, np, torch, stream)
     out["secondary"] = sec
