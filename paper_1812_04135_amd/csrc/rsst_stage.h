@@ -61,16 +61,35 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, int voff, in
   }
 }
 
-// Cell state at byte offsets (soff: workgroup-uniform plane offset, voff:
-// the thread's column) as FP64; `negv` >= 0 names a momentum component to
-// negate (mirror ghost); b: background index (FP32 perturbation form).
+// The stored values of a cell, as loaded (no conversion): the loads can be
+// issued early and their results used a phase later, with no wait in between.
+template <typename ST>
+__device__ __forceinline__ ST buf_load_raw(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  if constexpr (sizeof(ST) == 8) {
+    const u32x2_t v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    return __hiloint2double((int)v.y, (int)v.x);
+  } else {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  }
+}
+
 template <int NDIM, typename ST>
-__device__ __forceinline__ void load_cell(const StageArgs& A, __amdgpu_buffer_rsrc_t r, int soff,
-                                          int voff, int negv, int b, double (&u)[NDIM + 2]) {
-  constexpr int NV = NDIM + 2;
+__device__ __forceinline__ void load_cell_raw(const StageArgs& A, __amdgpu_buffer_rsrc_t r, int soff, int voff,
+                                              ST (&raw)[NDIM + 2]) {
   const int vstride = (int)(A.ncell * (long long)sizeof(ST));
 #pragma unroll
-  for (int v = 0; v < NV; ++v) u[v] = buf_load<ST>(r, voff, soff + v * vstride);
+  for (int v = 0; v < NDIM + 2; ++v) raw[v] = buf_load_raw<ST>(r, voff, soff + v * vstride);
+}
+
+// FP64 cell state from its stored values: widening and background (FP32
+// perturbation form, b its index), then the mirror negation of momentum
+// component `negv` (>= 0) for a ghost across a wall.
+template <int NDIM, typename ST>
+__device__ __forceinline__ void finish_cell(const StageArgs& A, const ST (&raw)[NDIM + 2], int negv, int b,
+                                            double (&u)[NDIM + 2]) {
+  constexpr int NV = NDIM + 2;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) u[v] = (double)raw[v];
   if constexpr (sizeof(ST) == 4) {
     // background along the march axis (or uniform): b is the same for the
     // whole workgroup, read through the scalar cache; otherwise per lane
@@ -86,6 +105,17 @@ __device__ __forceinline__ void load_cell(const StageArgs& A, __amdgpu_buffer_rs
 #pragma unroll
   for (int v = 1; v <= NDIM; ++v)
     if (v == negv) u[v] = -u[v];
+}
+
+// Cell state at byte offsets (soff: workgroup-uniform plane offset, voff:
+// the thread's column) as FP64; `negv` >= 0 names a momentum component to
+// negate (mirror ghost); b: background index (FP32 perturbation form).
+template <int NDIM, typename ST>
+__device__ __forceinline__ void load_cell(const StageArgs& A, __amdgpu_buffer_rsrc_t r, int soff,
+                                          int voff, int negv, int b, double (&u)[NDIM + 2]) {
+  ST raw[NDIM + 2];
+  load_cell_raw<NDIM, ST>(A, r, soff, voff, raw);
+  finish_cell<NDIM, ST>(A, raw, negv, b, u);
 }
 
 // Index of the background profile for cell (i, j, k) in kernel axes.
@@ -259,7 +289,7 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
   const int oc1 = o_lo ? clo1 : chi1, oc2 = o_lo ? clo2 : chi2;
   const int on1 = o_lo ? nlo1 : nhi1, on2 = o_lo ? nlo2 : nhi2;
   const int ob1 = o_lo ? blo1 : bhi1, ob2 = o_lo ? blo2 : bhi2;
-  double o1[NV], o2[NV], o3[ONE ? NV : 1], o4[ONE ? NV : 1];
+  ST o1[NV], o2[NV], o3[ONE ? NV : 1], o4[ONE ? NV : 1];  // stored values, finished at use
 
   double q0[NV], q1[NV], sm0[NV], Fm_lo[NV];
   double cmax = 0.0;
@@ -289,11 +319,11 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
     load_cell<NDIM, ST>(A, uin, 0, col, -1, bgi_xy, q0);
   }
   if (pre) {
-    load_cell<NDIM, ST>(A, uin, k0l * plane, oc1, on1, bg_on_m ? k0l : ob1, o1);
-    load_cell<NDIM, ST>(A, uin, k0l * plane, oc2, on2, bg_on_m ? k0l : ob2, o2);
+    load_cell_raw<NDIM, ST>(A, uin, k0l * plane, oc1, o1);
+    load_cell_raw<NDIM, ST>(A, uin, k0l * plane, oc2, o2);
     if constexpr (ONE) {
-      load_cell<NDIM, ST>(A, uin, k0l * plane, chi1, nhi1, bg_on_m ? k0l : bhi1, o3);
-      load_cell<NDIM, ST>(A, uin, k0l * plane, chi2, nhi2, bg_on_m ? k0l : bhi2, o4);
+      load_cell_raw<NDIM, ST>(A, uin, k0l * plane, chi1, o3);
+      load_cell_raw<NDIM, ST>(A, uin, k0l * plane, chi2, o4);
     }
   }
 
@@ -303,13 +333,17 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
     const int k = min(kraw, G.nm - 1);  // plane used for loads and stores
     const int koff = k * plane;
     // ---- loads for this iteration: the plane two ahead, the step-start state
-    double q2[NV], un[NV];
+    // (stored values now, finished where first used, so the loads overlap
+    // this plane's work)
+    ST q2r[NV], unr[NV];
+    int q2k = 0, q2neg = -1;
     if constexpr (HM) {
       bool n;
-      const int kk = map_index(min(kraw, G.nm - 1) + 2, G.nm, rm_lo, rm_hi, n);
-      load_cell<NDIM, ST>(A, uin, kk * plane, col, n ? NDIM : -1, bgk(kk), q2);
+      q2k = map_index(min(kraw, G.nm - 1) + 2, G.nm, rm_lo, rm_hi, n);
+      q2neg = n ? NDIM : -1;
+      load_cell_raw<NDIM, ST>(A, uin, q2k * plane, col, q2r);
     }
-    if constexpr (STAGE == 2) load_cell<NDIM, ST>(A, unp, koff, col, -1, bgk(k), un);
+    if constexpr (STAGE == 2) load_cell_raw<NDIM, ST>(A, unp, koff, col, unr);
 
     // ---- P1: publish this plane's cell state
     if constexpr (HS) {
@@ -386,8 +420,7 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
     if constexpr (HS) {
       double uD[NV], uU[NV], h[NV];
       if (first_row && pre) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) uD[v] = o1[v];
+        finish_cell<NDIM, ST>(A, o1, on1, bg_on_m ? k : ob1, uD);
       } else if (first_row) {
         load_cell<NDIM, ST>(A, uin, koff, clo1, nlo1, bg_on_m ? k : blo1, uD);
       } else {
@@ -395,8 +428,8 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
         for (int v = 0; v < NV; ++v) uD[v] = Urow[(v * TS + row - 1) * nxp + i_raw];
       }
       if (last_row && pre) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) uU[v] = ONE ? o3[ONE ? v : 0] : o1[v];
+        if constexpr (ONE) finish_cell<NDIM, ST>(A, o3, nhi1, bg_on_m ? k : bhi1, uU);
+        else finish_cell<NDIM, ST>(A, o1, on1, bg_on_m ? k : ob1, uU);
       } else if (last_row) {
         load_cell<NDIM, ST>(A, uin, koff, chi1, nhi1, bg_on_m ? k : bhi1, uU);
       } else {
@@ -415,8 +448,8 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
           // tile's upper face
           double u2[NV], hh[NV], Fh[NV];
           if (pre) {
-#pragma unroll
-            for (int v = 0; v < NV; ++v) u2[v] = ONE ? o4[ONE ? v : 0] : o2[v];
+            if constexpr (ONE) finish_cell<NDIM, ST>(A, o4, nhi2, bg_on_m ? k : bhi2, u2);
+            else finish_cell<NDIM, ST>(A, o2, on2, bg_on_m ? k : ob2, u2);
           } else {
             load_cell<NDIM, ST>(A, uin, koff, chi2, nhi2, bg_on_m ? k : bhi2, u2);
           }
@@ -435,8 +468,7 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
         // lower face
         double u2[NV], hh[NV], Fh[NV];
         if (pre) {
-#pragma unroll
-          for (int v = 0; v < NV; ++v) u2[v] = o2[v];
+          finish_cell<NDIM, ST>(A, o2, on2, bg_on_m ? k : ob2, u2);
         } else {
           load_cell<NDIM, ST>(A, uin, koff, clo2, nlo2, bg_on_m ? k : blo2, u2);
         }
@@ -451,11 +483,11 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
     }
     if (pre) {  // the outside rows of the next plane
       const int kn = min(kraw + 1, G.nm - 1);
-      load_cell<NDIM, ST>(A, uin, kn * plane, oc1, on1, bg_on_m ? kn : ob1, o1);
-      load_cell<NDIM, ST>(A, uin, kn * plane, oc2, on2, bg_on_m ? kn : ob2, o2);
+      load_cell_raw<NDIM, ST>(A, uin, kn * plane, oc1, o1);
+      load_cell_raw<NDIM, ST>(A, uin, kn * plane, oc2, o2);
       if constexpr (ONE) {
-        load_cell<NDIM, ST>(A, uin, kn * plane, chi1, nhi1, bg_on_m ? kn : bhi1, o3);
-        load_cell<NDIM, ST>(A, uin, kn * plane, chi2, nhi2, bg_on_m ? kn : bhi2, o4);
+        load_cell_raw<NDIM, ST>(A, uin, kn * plane, chi1, o3);
+        load_cell_raw<NDIM, ST>(A, uin, kn * plane, chi2, o4);
       }
     }
     __syncthreads();  // B2
@@ -523,7 +555,9 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
         Dl[v] = fma(-(hi - lo), hy, Dl[v]);
       }
     }
+    double q2[NV];
     if constexpr (HM) {
+      finish_cell<NDIM, ST>(A, q2r, q2neg, bgk(q2k), q2);
       double sm1[NV], Fm_hi[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) sm1[v] = mc_half(q1[v] - q0[v], q2[v] - q1[v]);
@@ -540,6 +574,8 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
     }
     double R[NV];
     const unsigned b = rsst_rate<NDIM, FORM, XCM>(q0, Dl, K, g, R);
+    double un[NV];
+    if constexpr (STAGE == 2) finish_cell<NDIM, ST>(A, unr, -1, bgk(k), un);
     if (active && kval) {
       bad |= b;
       const int bk = bgk(k);
