@@ -107,6 +107,29 @@ __device__ __forceinline__ void finish_cell(const StageArgs& A, const ST (&raw)[
     if (v == negv) u[v] = -u[v];
 }
 
+// FP64 cell state from its stored values with the background values bgv
+// already in registers (FP32 perturbation form), then the mirror sign.
+template <int NDIM, typename ST>
+__device__ __forceinline__ void finish_cell_bgv(const ST (&raw)[NDIM + 2], int negv, const double (&bgv)[NDIM + 2],
+                                                double (&u)[NDIM + 2]) {
+#pragma unroll
+  for (int v = 0; v < NDIM + 2; ++v) u[v] = (double)raw[v] + bgv[v];
+#pragma unroll
+  for (int v = 1; v <= NDIM; ++v)
+    if (v == negv) u[v] = -u[v];
+}
+
+// The NV background values at profile index idx, as vector loads (their
+// wait falls where they are used, not on the LDS counter).
+template <int NV>
+__device__ __forceinline__ void load_bg(__amdgpu_buffer_rsrc_t r, int nbg, int idx, double (&b)[NV]) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const u32x2_t x = __builtin_amdgcn_raw_buffer_load_b64(r, (v * nbg + idx) * 8, 0, 0);
+    b[v] = __hiloint2double((int)x.y, (int)x.x);
+  }
+}
+
 // Cell state at byte offsets (soff: workgroup-uniform plane offset, voff:
 // the thread's column) as FP64; `negv` >= 0 names a momentum component to
 // negate (mirror ghost); b: background index (FP32 perturbation form).
@@ -254,6 +277,19 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
   const int bgi_xy = (sizeof(ST) == 4 && !A.bg_uniform) ? bg_index<NDIM>(A, i, j, 0) : 0;
   const bool bg_on_m = (sizeof(ST) == 4) && (A.bg_axis == am) && HM;
   auto bgk = [&](int kk) { return bg_on_m ? kk : bgi_xy; };
+  // FP32 perturbation form: the background in registers.  Along the march
+  // axis: bgA holds plane k and bgB the plane two ahead, loaded at the top of
+  // each plane; otherwise (uniform, along x, along y) bgA holds this cell's
+  // values for the whole march.  Rows outside a 3D tile with a profile
+  // along y take the indexed path.
+  constexpr bool F32 = sizeof(ST) == 4;
+  const bool bg_rows = F32 && HS && A.bg_axis == 1;
+  double bgA[NV], bgB[NV];
+  const __amdgpu_buffer_rsrc_t bgr = field_rsrc(A.bg, F32 ? (long long)NV * A.nbg * 8 : 0);
+  if constexpr (F32) {
+    const int ib = A.bg_uniform ? 0 : bg_index<NDIM>(A, i, j, 0);
+    if (!bg_on_m) load_bg<NV>(bgr, A.nbg, ib, bgA);
+  }
 
   const Consts K{A.gamma, A.gm1, A.inv_gm1, A.inv_xi, A.f, A.inv_cmax2};
   const double g[3] = {A.g[0], A.g[1], A.g[2]};
@@ -344,6 +380,12 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
       load_cell_raw<NDIM, ST>(A, uin, q2k * plane, col, q2r);
     }
     if constexpr (STAGE == 2) load_cell_raw<NDIM, ST>(A, unp, koff, col, unr);
+    if constexpr (F32) {
+      if (bg_on_m) {
+        load_bg<NV>(bgr, A.nbg, k, bgA);
+        load_bg<NV>(bgr, A.nbg, q2k, bgB);
+      }
+    }
 
     // ---- P1: publish this plane's cell state
     if constexpr (HS) {
@@ -420,7 +462,8 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
     if constexpr (HS) {
       double uD[NV], uU[NV], h[NV];
       if (first_row && pre) {
-        finish_cell<NDIM, ST>(A, o1, on1, bg_on_m ? k : ob1, uD);
+        if (F32 && !bg_rows) finish_cell_bgv<NDIM, ST>(o1, on1, bgA, uD);
+        else finish_cell<NDIM, ST>(A, o1, on1, bg_on_m ? k : ob1, uD);
       } else if (first_row) {
         load_cell<NDIM, ST>(A, uin, koff, clo1, nlo1, bg_on_m ? k : blo1, uD);
       } else {
@@ -428,8 +471,13 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
         for (int v = 0; v < NV; ++v) uD[v] = Urow[(v * TS + row - 1) * nxp + i_raw];
       }
       if (last_row && pre) {
-        if constexpr (ONE) finish_cell<NDIM, ST>(A, o3, nhi1, bg_on_m ? k : bhi1, uU);
-        else finish_cell<NDIM, ST>(A, o1, on1, bg_on_m ? k : ob1, uU);
+        if constexpr (ONE) {
+          if (F32 && !bg_rows) finish_cell_bgv<NDIM, ST>(o3, nhi1, bgA, uU);
+          else finish_cell<NDIM, ST>(A, o3, nhi1, bg_on_m ? k : bhi1, uU);
+        } else {
+          if (F32 && !bg_rows) finish_cell_bgv<NDIM, ST>(o1, on1, bgA, uU);
+          else finish_cell<NDIM, ST>(A, o1, on1, bg_on_m ? k : ob1, uU);
+        }
       } else if (last_row) {
         load_cell<NDIM, ST>(A, uin, koff, chi1, nhi1, bg_on_m ? k : bhi1, uU);
       } else {
@@ -448,8 +496,13 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
           // tile's upper face
           double u2[NV], hh[NV], Fh[NV];
           if (pre) {
-            if constexpr (ONE) finish_cell<NDIM, ST>(A, o4, nhi2, bg_on_m ? k : bhi2, u2);
-            else finish_cell<NDIM, ST>(A, o2, on2, bg_on_m ? k : ob2, u2);
+            if constexpr (ONE) {
+              if (F32 && !bg_rows) finish_cell_bgv<NDIM, ST>(o4, nhi2, bgA, u2);
+              else finish_cell<NDIM, ST>(A, o4, nhi2, bg_on_m ? k : bhi2, u2);
+            } else {
+              if (F32 && !bg_rows) finish_cell_bgv<NDIM, ST>(o2, on2, bgA, u2);
+              else finish_cell<NDIM, ST>(A, o2, on2, bg_on_m ? k : ob2, u2);
+            }
           } else {
             load_cell<NDIM, ST>(A, uin, koff, chi2, nhi2, bg_on_m ? k : bhi2, u2);
           }
@@ -468,7 +521,8 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
         // lower face
         double u2[NV], hh[NV], Fh[NV];
         if (pre) {
-          finish_cell<NDIM, ST>(A, o2, on2, bg_on_m ? k : ob2, u2);
+          if (F32 && !bg_rows) finish_cell_bgv<NDIM, ST>(o2, on2, bgA, u2);
+          else finish_cell<NDIM, ST>(A, o2, on2, bg_on_m ? k : ob2, u2);
         } else {
           load_cell<NDIM, ST>(A, uin, koff, clo2, nlo2, bg_on_m ? k : blo2, u2);
         }
@@ -557,7 +611,8 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
     }
     double q2[NV];
     if constexpr (HM) {
-      finish_cell<NDIM, ST>(A, q2r, q2neg, bgk(q2k), q2);
+      if constexpr (F32) finish_cell_bgv<NDIM, ST>(q2r, q2neg, bg_on_m ? bgB : bgA, q2);
+      else finish_cell<NDIM, ST>(A, q2r, q2neg, bgk(q2k), q2);
       double sm1[NV], Fm_hi[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) sm1[v] = mc_half(q1[v] - q0[v], q2[v] - q1[v]);
@@ -575,18 +630,19 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
     double R[NV];
     const unsigned b = rsst_rate<NDIM, FORM, XCM>(q0, Dl, K, g, R);
     double un[NV];
-    if constexpr (STAGE == 2) finish_cell<NDIM, ST>(A, unr, -1, bgk(k), un);
+    if constexpr (STAGE == 2) {
+      if constexpr (F32) finish_cell_bgv<NDIM, ST>(unr, -1, bgA, un);
+      else finish_cell<NDIM, ST>(A, unr, -1, bgk(k), un);
+    }
     if (active && kval) {
       bad |= b;
-      const int bk = bgk(k);
       double out[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         double y = fma(dt, R[v], q0[v]);
         if constexpr (STAGE == 2) y = 0.5 * (un[v] + y);
         double bgv = 0.0;
-        if constexpr (sizeof(ST) == 4)
-          bgv = A.bg_uniform ? A.bg[v * A.nbg + __builtin_amdgcn_readfirstlane(bk)] : A.bg[v * A.nbg + bk];
+        if constexpr (F32) bgv = bgA[v];  // plane k (or this cell's invariant values)
         const ST st = (ST)(y - bgv);
         buf_store<ST>(uout, col, koff + v * vstride, st);
         out[v] = (double)st + bgv;
