@@ -38,7 +38,7 @@ struct StageArgs {
   double* scal;      // device scalars
   const void* uin;   // stage input (halo reads)
   const void* un;    // stage 2: state at the start of the step (pointwise)
-  void* uout;        // stage output
+  void* uout;        // stage output (stage 2: the same array as un, updated in place)
   const double* bg;  // FP32 perturbation form: background [nv][nbg]
   int bg_axis;       // -1 uniform
   int nbg;

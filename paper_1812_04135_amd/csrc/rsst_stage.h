@@ -183,7 +183,7 @@ __device__ __forceinline__ Face<NV> face_from_left(const Face<NV>& s) {
 
 // LDS carve-up of one workgroup (doubles).  3D only: Urow, Prow, Frow.
 struct Carve {
-  int urow, prow, frow, seamU, seamUl, seamM, seamP, seamPl, seamF, red, total;
+  int urow, prow, mrow, frow, seamU, seamUl, seamM, seamP, seamPl, red, total;
 };
 
 __host__ __device__ inline Carve carve(int ndim, int ts, int nwx) {
@@ -192,13 +192,13 @@ __host__ __device__ inline Carve carve(int ndim, int ts, int nwx) {
   int o = 0;
   c.urow = o;   if (ndim == 3) o += NV * ts * nxp;        // cell states, per row
   c.prow = o;   if (ndim == 3) o += PL * ts * nxp;        // y plus-face states
-  c.frow = o;   if (ndim == 3) o += NV * (ts + 1) * nxp;  // y fluxes at faces r - 1/2
+  c.mrow = o;   if (ndim == 3) o += PL * ts * nxp;        // y minus-face states
+  c.frow = o;   if (ndim == 3) o += NV * (ts + 1) * nxp;  // y fluxes at the tile's two outer faces
   c.seamU = o;  o += ts * nwx * 2 * NV;                   // lane 0 / lane 63 cell states
   c.seamUl = o; o += ts * NV;                             // last cell of each row
   c.seamM = o;  o += ts * nwx * PL;                       // lane 0 minus-face states
   c.seamP = o;  o += ts * nwx * PL;                       // lane 63 plus-face states
   c.seamPl = o; o += ts * PL;                             // last cell's plus-face state
-  c.seamF = o;  o += ts * (nwx + 1) * NV;                 // x fluxes at wave edges
   c.red = o;    o += 16;
   c.total = o;
   return c;
@@ -238,13 +238,13 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
   const Carve C = carve(NDIM, TS, nwx);
   double* Urow = lds + C.urow;      // [NV][TS][nxp]
   double* Prow = lds + C.prow;      // [PL][TS][nxp]
-  double* Frow = lds + C.frow;      // [NV][TS+1][nxp]
+  double* Mrow = lds + C.mrow;      // [PL][TS][nxp]
+  double* Frow = lds + C.frow;      // [NV][TS+1][nxp] (slots 0 and ts_eff)
   double* seamU = lds + C.seamU;    // [TS][nwx][2][NV]
   double* seamUl = lds + C.seamUl;  // [TS][NV]
   double* seamM = lds + C.seamM;    // [TS][nwx][PL]
   double* seamP = lds + C.seamP;    // [TS][nwx][PL]
   double* seamPl = lds + C.seamPl;  // [TS][PL]
-  double* seamF = lds + C.seamF;    // [TS][nwx+1][NV]
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -296,7 +296,9 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
   const double hx = 0.5 * A.inv_dx[0], hy = 0.5 * A.inv_dx[1], hz = 0.5 * A.inv_dx[DM];
   const __amdgpu_buffer_rsrc_t uin = field_rsrc(A.uin, fbytes);
   const __amdgpu_buffer_rsrc_t unp = field_rsrc(A.un ? A.un : A.uin, fbytes);
-  const __amdgpu_buffer_rsrc_t uout = field_rsrc(A.uout, fbytes);
+  // stage 2 writes the new state in place over the step-start state (the
+  // callers pass uout == un), so one resource serves both
+  const __amdgpu_buffer_rsrc_t uout = STAGE == 2 ? unp : field_rsrc(A.uout, fbytes);
   const int vstride = (int)(A.ncell * (long long)SZ);
 
   // y rows just outside the tile (3D): columns and mirror flags, once
@@ -516,6 +518,7 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
         }
       }
       make_face<NDIM, 1, XCM>(q0, h, false, K, fym);
+      put_face(Mrow + row * nxp + i_raw, TS * nxp, fym);
       if (first_row) {
         // plus state of the row below the tile, and the flux at the tile's
         // lower face
@@ -546,68 +549,68 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
     }
     __syncthreads();  // B2
 
-    // ---- P3: x fluxes at the wave edges (lanes 0..nwx of wave 0 of each
-    // row), y fluxes at the faces inside the tile
-    if (wx == 0 && lane <= nwx && !wave_idle) {
-      const int e = lane;  // face at the left edge of wave e (e = nwx: row end)
-      Face<NV> fl, fr;
-      if (e == 0) {
-        get_face(seamM + (row * nwx) * PL, 1, fr);
-        if (x_per) get_face(seamPl + row * PL, 1, fl);
-        else fl = mirror<NDIM, 0>(fr);
-      } else if (e == nwx) {
-        get_face(seamPl + row * PL, 1, fl);
-        if (x_per) get_face(seamM + (row * nwx) * PL, 1, fr);
-        else fr = mirror<NDIM, 0>(fl);
-      } else {
-        get_face(seamP + (row * nwx + e - 1) * PL, 1, fl);
-        get_face(seamM + (row * nwx + e) * PL, 1, fr);
-      }
-      double Fe[NV];
-      flux2<NDIM, 0>(fl, fr, Fe);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) seamF[(row * (nwx + 1) + e) * NV + v] = Fe[v];
-    }
-    if constexpr (HS) {
-      if (row >= 1 && row < ts_eff) {
-        Face<NV> pd;
-        double Fy[NV];
-        get_face(Prow + (row - 1) * nxp + i_raw, TS * nxp, pd);
-        flux2<NDIM, 1>(pd, fym, Fy);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) Frow[(v * (TS + 1) + row) * nxp + i_raw] = Fy[v];
-      }
-    }
-    __syncthreads();  // B3
-
-    // ---- P4: divergence, march face, correction, update
+    // ---- P3: the fluxes of the faces shared with another wave or row.  The
+    // x faces at a wave's edges are formed by the edge lanes of both waves
+    // that share them, from the seam face states; the y faces inside the
+    // tile by both rows that share them, from the row face states.  A flux is
+    // the same function of the same face states wherever it is formed, so
+    // its bits do not depend on who forms it, and no third barrier is needed.
     double Dl[NV];
     {
       double Fx_hi[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) Fx_hi[v] = from_right(Fx_lo[v]);
-      if (lane == 0) {
+      const bool edge_r = last_x || (lane == 63 && xin);
+      if ((lane == 0 || edge_r) && !wave_idle) {
+        Face<NV> fl, fr;
+        if (lane == 0) {  // face at the wave's left edge
+          get_face(seamM + (row * nwx + wx) * PL, 1, fr);
+          if (wx > 0) get_face(seamP + (row * nwx + wx - 1) * PL, 1, fl);
+          else if (x_per) get_face(seamPl + row * PL, 1, fl);
+          else fl = mirror<NDIM, 0>(fr);
+        } else if (last_x) {  // face at the row's end
+          get_face(seamPl + row * PL, 1, fl);
+          if (x_per) get_face(seamM + (row * nwx) * PL, 1, fr);
+          else fr = mirror<NDIM, 0>(fl);
+        } else {  // face at the wave's right edge
+          get_face(seamP + (row * nwx + wx) * PL, 1, fl);
+          get_face(seamM + (row * nwx + wx + 1) * PL, 1, fr);
+        }
+        double Fe[NV];
+        flux2<NDIM, 0>(fl, fr, Fe);
+        if (lane == 0) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) Fx_lo[v] = seamF[(row * (nwx + 1) + wx) * NV + v];
-      }
-      if (last_x) {
+          for (int v = 0; v < NV; ++v) Fx_lo[v] = Fe[v];
+        } else {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) Fx_hi[v] = seamF[(row * (nwx + 1) + nwx) * NV + v];
-      } else if (lane == 63 && xin) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) Fx_hi[v] = seamF[(row * (nwx + 1) + wx + 1) * NV + v];
+          for (int v = 0; v < NV; ++v) Fx_hi[v] = Fe[v];
+        }
       }
 #pragma unroll
       for (int v = 0; v < NV; ++v) Dl[v] = -(Fx_hi[v] - Fx_lo[v]) * hx;
     }
     if constexpr (HS) {
-      const int ru = min(row + 1, TS);
+      double lo[NV], hi[NV];
+      if (first_row) {
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const double lo = Frow[(v * (TS + 1) + row) * nxp + i_raw];
-        const double hi = Frow[(v * (TS + 1) + ru) * nxp + i_raw];
-        Dl[v] = fma(-(hi - lo), hy, Dl[v]);
+        for (int v = 0; v < NV; ++v) lo[v] = Frow[(v * (TS + 1)) * nxp + i_raw];
+      } else {
+        Face<NV> pd;
+        get_face(Prow + (row - 1) * nxp + i_raw, TS * nxp, pd);
+        flux2<NDIM, 1>(pd, fym, lo);
       }
+      if (last_row) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) hi[v] = Frow[(v * (TS + 1) + ts_eff) * nxp + i_raw];
+      } else {
+        const int ru = min(row + 1, TS - 1);  // rows past a ragged tile read in range
+        Face<NV> pu, mu;
+        get_face(Prow + row * nxp + i_raw, TS * nxp, pu);
+        get_face(Mrow + ru * nxp + i_raw, TS * nxp, mu);
+        flux2<NDIM, 1>(pu, mu, hi);
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Dl[v] = fma(-(hi[v] - lo[v]), hy, Dl[v]);
     }
     double q2[NV];
     if constexpr (HM) {
