@@ -153,3 +153,32 @@ def test_autotuner_sets_tiles_caches_and_keeps_results(tmp_path):
     for q, ((cfg, U0n), Ub) in enumerate(zip(boxes, outs)):
         Us, _ = _single(cfg, U0n, 5)
         assert np.array_equal(Ub, Us), q
+
+
+def test_batch_full_size_sampled_boxes():
+    """The batched workload at full size (512 stratified boxes, N in 64..256,
+    xi in 1..50, FP32 perturbation, 200 steps, one launch): the smallest, the
+    median and the largest box against the FP64 oracle over all 200 steps."""
+    boxes = W.batch2d(nbox=512)
+    cfgs = [c for c, _, _ in boxes]
+    nst = 200
+    B = R.Batch(cfgs, prec="fp32_pert", bgs=[m["bg"] for _, _, m in boxes], max_steps=nst)
+    starts = [(U - m["bg"][:, :, None]).astype(np.float32) for _, U, m in boxes]
+    U = B.pack(starts)
+    B.run(U, nst)
+    torch.cuda.synchronize()
+    assert B.poll() == 0
+    outs = B.unpack(U)
+    sizes = [int(c["n"][0]) for c in cfgs]
+    order = np.argsort(sizes, kind="stable")
+    for q in (int(order[0]), int(order[len(order) // 2]), int(order[-1])):
+        cfg, _, meta = boxes[q]
+        bg = meta["bg"][:, :, None]
+        Uo, _, _ = oracle.run(cfg, bg + starts[q].astype(np.float64), nst)
+        pert = Uo - bg
+        s = [np.abs(pert[v]).max() for v in range(4)]
+        sm = max(s[1:3])
+        s = [s[0], sm, sm, s[3]]
+        err = max(float(np.abs(outs[q][v].astype(np.float64) - pert[v]).max() / s[v]) for v in range(4))
+        print(f"[batch full] box {q} N={cfg['n'][0]} xi={cfg['xi']:.2f} err/|pert| = {err:.2e}", flush=True)
+        assert err <= 1e-5, (q, err)
