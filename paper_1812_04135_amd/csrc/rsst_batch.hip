@@ -147,7 +147,7 @@ __device__ __forceinline__ void signal_done(const BatchState& S, const Pending& 
 // otherwise join the two across the back edge into a loop that thread 0
 // leaves while the rest of its wave goes round without it.
 template <typename ST, int FORM>
-__global__ void __launch_bounds__(kBatchThreads) batch_kernel(const BoxDev* __restrict__ boxes,
+__global__ void __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(3))) batch_kernel(const BoxDev* __restrict__ boxes,
                                                             const Item* __restrict__ items,
                                                             BatchState S) {
   extern __shared__ double lds[];
