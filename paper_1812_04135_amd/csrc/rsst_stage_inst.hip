@@ -38,9 +38,17 @@ static hipError_t launch_stage_k(const StageArgs& a, hipStream_t s) {
   const Geometry& G = a.geo;
   const dim3 grid((unsigned)(G.ntile_s * G.nchunk)), block((unsigned)G.threads);
   auto kern = stage_kernel<NDIM, STAGE, ST, FORM, NWXC>;
-  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)G.lds_bytes);
-  if (e != hipSuccess) return e;
+  // raise the kernel's LDS limit only when a larger tile needs it, so launches
+  // of a known shape (e.g. under HIP graph capture) make no attribute call
+  static int lds_set[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  if ((int)G.lds_bytes > lds_set[dev]) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)G.lds_bytes);
+    if (e != hipSuccess) return e;
+    lds_set[dev] = (int)G.lds_bytes;
+  }
   hipLaunchKernelGGL(kern, grid, block, G.lds_bytes, s, a);
   return hipGetLastError();
 }

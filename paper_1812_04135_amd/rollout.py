@@ -9,9 +9,11 @@ backward re-runs each segment forward from its checkpoint (device tensors
 only) and then runs the segment's adjoint steps in reverse.
 
 The time step is frozen: dt is an input, not the CFL rule, so the gradient
-is that of the map U0 -> U_N at fixed dt.  Every step, forward and adjoint,
-runs in the library's kernels; this module orders the calls and owns the
-checkpoint tensors.
+is that of the map U0 -> U_N at fixed dt.  The backward of a segment is
+captured once as a HIP graph and replayed for the other segments of the
+same length (the kernels and their order are those of the eager path).
+Every step, forward and adjoint, runs in the library's kernels; this module
+orders the calls and owns the checkpoint tensors.
 """
 from __future__ import annotations
 
@@ -22,7 +24,7 @@ from . import Solver
 
 class RSSTRollout(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, U0, xi, cfg, nsteps, dt, checkpoint_every=20):
+    def forward(ctx, U0, xi, cfg, nsteps, dt, checkpoint_every=20, use_graph=True):
         if U0.dtype != torch.float64 or not U0.is_cuda:
             raise TypeError("RSSTRollout: U0 must be a float64 CUDA tensor")
         nsteps, K = int(nsteps), max(1, int(checkpoint_every))
@@ -36,8 +38,20 @@ class RSSTRollout(torch.autograd.Function):
             if (n + 1) % K == 0 and n + 1 < nsteps:
                 ckpts.append(U.clone())
         ctx.solver, ctx.ckpts, ctx.nsteps, ctx.dt, ctx.K = solver, ckpts, nsteps, float(dt), K
+        ctx.use_graph = bool(use_graph)
         ctx.xi_needs_grad = isinstance(xi, torch.Tensor) and xi.requires_grad
         return U
+
+    @staticmethod
+    def _segment(solver, states, lam, dxi, dt, m):
+        """Re-run m - 1 steps from states[0] into states[1..], then pull lam
+        back through the m steps (the states must already hold the
+        checkpoint in states[0])."""
+        for i in range(1, m):
+            states[i].copy_(states[i - 1])
+            solver.step(states[i], dt)
+        for n in reversed(range(m)):
+            solver.adjoint_step(states[n], lam, dt, dxi)
 
     @staticmethod
     def backward(ctx, gU):
@@ -45,26 +59,46 @@ class RSSTRollout(torch.autograd.Function):
         lam = gU.detach().to(torch.float64).contiguous().clone()
         dxi = torch.zeros(1, dtype=torch.float64, device=lam.device)
         nseg = len(ctx.ckpts)
+        states = [torch.empty_like(lam) for _ in range(min(K, nsteps))]
+        graphs = {}
         for seg in reversed(range(nseg)):
             n0, n1 = seg * K, min((seg + 1) * K, nsteps)
-            states = [ctx.ckpts[seg].clone()]
-            for _ in range(n0, n1 - 1):
-                u = states[-1].clone()
-                solver.step(u, dt)
-                states.append(u)
-            for n in reversed(range(n0, n1)):
-                solver.adjoint_step(states[n - n0], lam, dt, dxi)
-            del states
+            m = n1 - n0
+            states[0].copy_(ctx.ckpts[seg])
+            if not ctx.use_graph or nseg < 3:
+                RSSTRollout._segment(solver, states, lam, dxi, dt, m)
+                continue
+            if m not in graphs:
+                # first segment of this length runs eagerly (it also sets up
+                # the kernels), later ones replay a HIP graph of the same
+                # launches: forward re-run and adjoint steps
+                RSSTRollout._segment(solver, states, lam, dxi, dt, m)
+                g = torch.cuda.CUDAGraph()
+                lam_in = lam.clone()
+                dxi_in = dxi.clone()
+                torch.cuda.synchronize()
+                with torch.cuda.graph(g):
+                    RSSTRollout._segment(solver, states, lam, dxi, dt, m)
+                # capturing does not run the work: restore the cotangents
+                lam.copy_(lam_in)
+                dxi.copy_(dxi_in)
+                graphs[m] = g
+                continue
+            graphs[m].replay()
+        torch.cuda.synchronize()
+        graphs.clear()
         solver.close()
         ctx.ckpts = None
         gxi = dxi.reshape(()) if ctx.xi_needs_grad else None
-        return lam, gxi, None, None, None, None
+        return lam, gxi, None, None, None, None, None
 
 
-def rollout(U0, xi, cfg, nsteps, dt, checkpoint_every=20):
+def rollout(U0, xi, cfg, nsteps, dt, checkpoint_every=20, use_graph=True):
     """Final state of nsteps fixed-dt steps from U0 (differentiable in U0
-    and, if xi is a tensor that requires grad, in xi)."""
-    return RSSTRollout.apply(U0, xi, cfg, nsteps, dt, checkpoint_every)
+    and, if xi is a tensor that requires grad, in xi).  use_graph: replay
+    the backward of each checkpoint segment from a HIP graph (same kernels,
+    fewer host launches)."""
+    return RSSTRollout.apply(U0, xi, cfg, nsteps, dt, checkpoint_every, use_graph)
 
 
 def kinetic_energy(U, cfg):

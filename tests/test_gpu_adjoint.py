@@ -247,3 +247,23 @@ def test_adjoint_full_size_finite_differences():
         print(f"[fd full] dir {q}: fd {fd:.10e} adjoint {ad:.10e} rel {abs(fd - ad) / abs(ad):.2e}", flush=True)
         assert abs(fd - ad) <= 1e-4 * abs(ad)
     s.close()
+
+
+@pytest.mark.parametrize("K", [20, 15])
+def test_rollout_graph_replays_equal_eager(K):
+    """The backward replayed from HIP graphs (one capture per segment length,
+    replayed for every other segment, with eager copies of the checkpoints
+    between replays) gives the same bits as the eager backward."""
+    from paper_1812_04135_amd.rollout import kinetic_energy, rollout
+    cfg, U0 = W.random_state(2, [24, 20], seed_k=731, xi=6.0, form="pms",
+                             bc_lo=["periodic", "reflect"], g=[0.0, -0.3], mach=0.1)
+    dt = 0.4 * oracle.cfl_dt(cfg, U0)
+    res = []
+    for use_graph in (False, True, True):
+        U = torch.from_numpy(U0).cuda().requires_grad_(True)
+        xi = torch.tensor(cfg["xi"], dtype=torch.float64, requires_grad=True)
+        J = kinetic_energy(rollout(U, xi, cfg, 100, dt, checkpoint_every=K, use_graph=use_graph), cfg)
+        J.backward()
+        res.append((U.grad.cpu().numpy(), float(xi.grad)))
+    for g, x in res[1:]:
+        assert np.array_equal(g, res[0][0]) and x == res[0][1]
