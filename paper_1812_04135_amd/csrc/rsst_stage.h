@@ -181,7 +181,7 @@ __device__ __forceinline__ Face<NV> face_from_left(const Face<NV>& s) {
 
 // ---------------------------------------------------------------- stage
 
-// LDS carve-up of one workgroup (doubles).  3D only: Urow, Prow, Frow.
+// LDS carve-up of one workgroup (doubles).  3D only: Urow, Prow, Mrow, Frow.
 struct Carve {
   int urow, prow, mrow, frow, seamU, seamUl, seamM, seamP, seamPl, red, total;
 };
@@ -191,9 +191,11 @@ __host__ __device__ inline Carve carve(int ndim, int ts, int nwx) {
   Carve c;
   int o = 0;
   c.urow = o;   if (ndim == 3) o += NV * ts * nxp;        // cell states, per row
-  c.prow = o;   if (ndim == 3) o += PL * ts * nxp;        // y plus-face states
-  c.mrow = o;   if (ndim == 3) o += PL * ts * nxp;        // y minus-face states
-  c.frow = o;   if (ndim == 3) o += NV * (ts + 1) * nxp;  // y fluxes at the tile's two outer faces
+  // the y face states that another row of the tile reads: the plus state of
+  // every row but the last, the minus state of every row but the first
+  c.prow = o;   if (ndim == 3) o += PL * (ts - 1) * nxp;
+  c.mrow = o;   if (ndim == 3) o += PL * (ts - 1) * nxp;
+  c.frow = o;   if (ndim == 3) o += NV * 2 * nxp;         // y fluxes at the tile's two outer faces
   c.seamU = o;  o += ts * nwx * 2 * NV;                   // lane 0 / lane 63 cell states
   c.seamUl = o; o += ts * NV;                             // last cell of each row
   c.seamM = o;  o += ts * nwx * PL;                       // lane 0 minus-face states
@@ -237,9 +239,10 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
 
   const Carve C = carve(NDIM, TS, nwx);
   double* Urow = lds + C.urow;      // [NV][TS][nxp]
-  double* Prow = lds + C.prow;      // [PL][TS][nxp]
-  double* Mrow = lds + C.mrow;      // [PL][TS][nxp]
-  double* Frow = lds + C.frow;      // [NV][TS+1][nxp] (slots 0 and ts_eff)
+  double* Prow = lds + C.prow;      // [PL][TS-1][nxp], slot r: row r
+  double* Mrow = lds + C.mrow;      // [PL][TS-1][nxp], slot r: row r + 1
+  double* Frow = lds + C.frow;      // [NV][2][nxp]: lower and upper outer face
+  const int PS = (TS - 1) * nxp;    // stride of one payload value in Prow, Mrow
   double* seamU = lds + C.seamU;    // [TS][nwx][2][NV]
   double* seamUl = lds + C.seamUl;  // [TS][NV]
   double* seamM = lds + C.seamM;    // [TS][nwx][PL]
@@ -492,7 +495,7 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
       {
         Face<NV> fyp;
         make_face<NDIM, 1, XCM>(q0, h, true, K, fyp);
-        put_face(Prow + row * nxp + i_raw, TS * nxp, fyp);
+        if (row < ts_eff - 1) put_face(Prow + row * nxp + i_raw, PS, fyp);
         if (last_row) {
           // minus state of the row above the tile, and the flux at the
           // tile's upper face
@@ -514,11 +517,11 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
           make_face<NDIM, 1, XCM>(uU, hh, false, K, fh);
           flux2<NDIM, 1>(fyp, fh, Fh);
 #pragma unroll
-          for (int v = 0; v < NV; ++v) Frow[(v * (TS + 1) + ts_eff) * nxp + i_raw] = Fh[v];
+          for (int v = 0; v < NV; ++v) Frow[(v * 2 + 1) * nxp + i_raw] = Fh[v];
         }
       }
       make_face<NDIM, 1, XCM>(q0, h, false, K, fym);
-      put_face(Mrow + row * nxp + i_raw, TS * nxp, fym);
+      if (row >= 1) put_face(Mrow + (row - 1) * nxp + i_raw, PS, fym);
       if (first_row) {
         // plus state of the row below the tile, and the flux at the tile's
         // lower face
@@ -535,7 +538,7 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
         make_face<NDIM, 1, XCM>(uD, hh, true, K, fh);
         flux2<NDIM, 1>(fh, fym, Fh);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) Frow[(v * (TS + 1)) * nxp + i_raw] = Fh[v];
+        for (int v = 0; v < NV; ++v) Frow[(v * 2) * nxp + i_raw] = Fh[v];
       }
     }
     if (pre) {  // the outside rows of the next plane
@@ -593,20 +596,21 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
       double lo[NV], hi[NV];
       if (first_row) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) lo[v] = Frow[(v * (TS + 1)) * nxp + i_raw];
+        for (int v = 0; v < NV; ++v) lo[v] = Frow[(v * 2) * nxp + i_raw];
       } else {
         Face<NV> pd;
-        get_face(Prow + (row - 1) * nxp + i_raw, TS * nxp, pd);
+        get_face(Prow + (row - 1) * nxp + i_raw, PS, pd);
         flux2<NDIM, 1>(pd, fym, lo);
       }
       if (last_row) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) hi[v] = Frow[(v * (TS + 1) + ts_eff) * nxp + i_raw];
+        for (int v = 0; v < NV; ++v) hi[v] = Frow[(v * 2 + 1) * nxp + i_raw];
       } else {
-        const int ru = min(row + 1, TS - 1);  // rows past a ragged tile read in range
+        // rows past a ragged tile read in range (their results are not stored)
+        const int rp = max(min(row, TS - 2), 0);
         Face<NV> pu, mu;
-        get_face(Prow + row * nxp + i_raw, TS * nxp, pu);
-        get_face(Mrow + ru * nxp + i_raw, TS * nxp, mu);
+        get_face(Prow + rp * nxp + i_raw, PS, pu);
+        get_face(Mrow + rp * nxp + i_raw, PS, mu);
         flux2<NDIM, 1>(pu, mu, hi);
       }
 #pragma unroll

@@ -16,8 +16,16 @@
 namespace rsstk {
 
 // FORM: the correction form, plus 8 when xi follows the sound speed (eq. cx).
+#ifndef RSST_LB3
+#define RSST_LB3 512
+#endif
+#ifndef RSST_WPE3
+#define RSST_WPE3 1
+#endif
+
 template <int NDIM, int STAGE, typename ST, int FORM, int NWXC>
-__global__ void __launch_bounds__(NDIM == 3 ? 512 : 1024) stage_kernel(const StageArgs A) {
+__global__ void __launch_bounds__(NDIM == 3 ? RSST_LB3 : 1024)
+    __attribute__((amdgpu_waves_per_eu(NDIM == 3 ? RSST_WPE3 : 1))) stage_kernel(const StageArgs A) {
   extern __shared__ double lds[];
   const Geometry& G = A.geo;
   const int L = xcd_tile(blockIdx.x, gridDim.x);
