@@ -22,6 +22,7 @@ _LIB = os.path.join(_HERE, "librsst_oracle.so")
 
 FORMS = {"euler": 0, "pvs": 1, "pms": 2, "dvs": 3, "dms": 4, "pd": 5}
 BCS = {"periodic": 0, "reflect": 1}
+EOS = {"ideal": 0, "vdw": 1}
 
 
 def build(force: bool = True) -> str:
@@ -49,6 +50,9 @@ class _Config(ctypes.Structure):
         ("bc_hi", ctypes.c_int * 3),
         ("form", ctypes.c_int),
         ("cmax", ctypes.c_double),
+        ("eos", ctypes.c_int),
+        ("eos_a", ctypes.c_double),
+        ("eos_b", ctypes.c_double),
     ]
 
 
@@ -58,7 +62,7 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build(force=True)
         lib = ctypes.CDLL(_LIB)
         dp = ctypes.POINTER(ctypes.c_double)
@@ -85,6 +89,12 @@ def _load():
         lib.ora_diag.argtypes = [cp, dp, dp]
         lib.ora_threads.restype = ctypes.c_int
         lib.ora_set_threads.argtypes = [ctypes.c_int]
+        lib.ora_eos.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_double, ctypes.c_double, dp]
+        lib.ora_prim_eos.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_double, dp, dp]
+        lib.ora_correct_eos.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp, dp, dp]
         _lib = lib
     return _lib
 
@@ -129,6 +139,10 @@ def make_config(cfg: dict) -> _Config:
     f = cfg.get("form", "pvs")
     c.form = FORMS[f] if isinstance(f, str) else int(f)
     c.cmax = float(cfg.get("cmax", 0.0))
+    e = cfg.get("eos", "ideal")
+    c.eos = EOS[e] if isinstance(e, str) else int(e)
+    c.eos_a = float(cfg.get("eos_a", 0.0))
+    c.eos_b = float(cfg.get("eos_b", 0.0))
     return c
 
 
@@ -152,11 +166,32 @@ def set_threads(n: int) -> None:
 
 # ----------------------------------------------------------------- per cell
 
-def prim(u, ndim: int, gamma: float, xi: float = 1.0, cmax: float = 0.0) -> dict:
+def _gas(gas):
+    """(kind, a, b) of an equation-of-state dict {eos, eos_a, eos_b}; None: ideal."""
+    if gas is None:
+        return 0, 0.0, 0.0
+    e = gas.get("eos", "ideal")
+    return (EOS[e] if isinstance(e, str) else int(e)), float(gas.get("eos_a", 0.0)), float(gas.get("eos_b", 0.0))
+
+
+def eos(gamma: float, rho: float, P: float, gas=None) -> dict:
+    """The equation of state at (rho, P): e(rho, P), P(rho, e) of that e,
+    (de/dP)_rho, (de/drho)_P and a^2."""
+    k, a, b = _gas(gas)
+    out = np.zeros(5)
+    _load().ora_eos(float(gamma), k, a, b, float(rho), float(P), _ptr(out))
+    return {"e": out[0], "P_of_e": out[1], "dedP": out[2], "dedrho": out[3], "a2": out[4]}
+
+
+def prim(u, ndim: int, gamma: float, xi: float = 1.0, cmax: float = 0.0, gas=None) -> dict:
     lib = _load()
     u = _vec(u, ndim + 2)
     out = np.zeros(9)
-    lib.ora_prim(ndim, gamma, xi, cmax, _ptr(u), _ptr(out))
+    if gas is not None:
+        assert cmax == 0.0
+        lib.ora_prim_eos(ndim, gamma, *_gas(gas), xi, _ptr(u), _ptr(out))
+    else:
+        lib.ora_prim(ndim, gamma, xi, cmax, _ptr(u), _ptr(out))
     return {"rho": out[0], "v": out[1:1 + ndim].copy(), "P": out[4], "a2": out[5],
             "a": out[6], "vabs": out[7], "ctot": out[8]}
 
@@ -190,13 +225,18 @@ def llf(UL, UR, ndim: int, gamma: float, xi: float, d: int) -> np.ndarray:
     return F
 
 
-def correct(u, D, ndim: int, gamma: float, xi: float, form, g=(0.0, 0.0, 0.0), cmax: float = 0.0) -> np.ndarray:
+def correct(u, D, ndim: int, gamma: float, xi: float, form, g=(0.0, 0.0, 0.0), cmax: float = 0.0,
+            gas=None) -> np.ndarray:
     lib = _load()
     u, D = _vec(u, ndim + 2), _vec(D, ndim + 2)
     gg = _vec(list(g) + [0.0] * 3)
     R = np.zeros(ndim + 2)
     fi = FORMS[form] if isinstance(form, str) else int(form)
-    lib.ora_correct(ndim, gamma, xi, cmax, fi, _ptr(u), _ptr(D), _ptr(gg), _ptr(R))
+    if gas is not None:
+        assert cmax == 0.0
+        lib.ora_correct_eos(ndim, gamma, *_gas(gas), xi, fi, _ptr(u), _ptr(D), _ptr(gg), _ptr(R))
+    else:
+        lib.ora_correct(ndim, gamma, xi, cmax, fi, _ptr(u), _ptr(D), _ptr(gg), _ptr(R))
     return R
 
 

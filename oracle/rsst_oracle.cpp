@@ -22,7 +22,10 @@
 //     with Delta P unchanged (App. B);
 //   * second-order SSP Runge-Kutta in time, CFL number 0.4 with c_tot.
 // Ideal gas: e = P/(gamma-1), a^2 = gamma P / rho, (de/dP)_rho = 1/(gamma-1),
-// (de/drho)_P = 0 (Sec. 3.2, after eq. pvs_cons_therm).
+// (de/drho)_P = 0 (Sec. 3.2, after eq. pvs_cons_therm).  General equation of
+// state (the formulation of Sec. 3.2 holds for any e(rho, P)): a van der Waals
+// gas, whose (de/dP)_rho, (de/drho)_P and a^2 enter through eq. pvs_cons_dpr
+// and eq. pvs_cons_therm (see Gas below).
 //
 // Readings where the paper is silent (each also listed in the design notes):
 //   * multi-D time step: dt = C * h / max(c_tot), h = 1/sum_d(1/dx_d)
@@ -66,6 +69,9 @@ typedef struct {
   int bc_hi[3];
   int form;        // 0 Euler, 1 PVS, 2 PMS, 3 DVS, 4 DMS, 5 PD
   double cmax;     // > 0: xi from the upper limit of the sound speed (eq. cx)
+  int eos;         // 0 ideal gas, 1 van der Waals gas (eos_a, eos_b)
+  double eos_a;    // van der Waals attraction a
+  double eos_b;    // van der Waals co-volume b
 } ora_config;
 
 }  // extern "C"
@@ -129,6 +135,71 @@ struct Prim {
   S rho, v[3], P, a2, a, vabs, ctot;
 };
 
+// The equation of state.  kind 0: ideal gas with ratio gamma.  kind 1: van der
+// Waals gas with constant specific heat at constant volume c_v and gas
+// constant (gamma-1) c_v: P = rho R T/(1 - b rho) - a rho^2 and internal
+// energy per unit mass c_v T - a rho, so the internal energy per unit volume
+// is
+//   e(rho, P) = (P + a rho^2)(1 - b rho)/(gamma-1) - a rho^2.
+// The paper uses such a gas for tests it does not report, with parameters it
+// does not give; a = b = 0 is the ideal gas.
+struct Gas {
+  double gamma;
+  int kind;
+  double a, b;
+};
+
+static inline Gas ideal_gas(double gamma) { return Gas{gamma, 0, 0.0, 0.0}; }
+
+// Internal energy density e(rho, P).
+template <class S>
+static S eos_e(const Gas& g, const S& rho, const S& P) {
+  if (g.kind == 0) return P / (g.gamma - 1.0);
+  return (P + g.a * rho * rho) * (1.0 - g.b * rho) / (g.gamma - 1.0) - g.a * rho * rho;
+}
+
+// Pressure P(rho, e): e(rho, P) above solved for P.
+template <class S>
+static S eos_P(const Gas& g, const S& rho, const S& e) {
+  if (g.kind == 0) return (g.gamma - 1.0) * e;
+  return (g.gamma - 1.0) * (e + g.a * rho * rho) / (1.0 - g.b * rho) - g.a * rho * rho;
+}
+
+// (de/dP)_rho of e(rho, P) above.
+template <class S>
+static S eos_dedP(const Gas& g, const S& rho) {
+  if (g.kind == 0) return S(1.0 / (g.gamma - 1.0));
+  return (1.0 - g.b * rho) / (g.gamma - 1.0);
+}
+
+// (de/drho)_P of e(rho, P) above (product rule on each factor).
+template <class S>
+static S eos_dedrho(const Gas& g, const S& rho, const S& P) {
+  if (g.kind == 0) return S(0.0);
+  return (2.0 * g.a * rho * (1.0 - g.b * rho) - g.b * (P + g.a * rho * rho)) / (g.gamma - 1.0)
+         - 2.0 * g.a * rho;
+}
+
+// Squared sound speed.  Eq. pvs_cons_therm gives (de/dP)_rho = rho T / P_S and
+// (de/drho)_P = (e+P)/rho - rho T a^2 / P_S; eliminating rho T / P_S,
+//   a^2 = [(e + P)/rho - (de/drho)_P] / (de/dP)_rho,
+// which for the ideal gas is gamma P / rho (written so for that gas).
+template <class S>
+static S eos_a2(const Gas& g, const S& rho, const S& P) {
+  if (g.kind == 0) return g.gamma * P / rho;
+  const S e = eos_e(g, rho, P);
+  return ((e + P) / rho - eos_dedrho(g, rho, P)) / eos_dedP(g, rho);
+}
+
+// Whether the gas state is physical: rho > 0 and P > 0, plus b rho < 1 and
+// a^2 > 0 for the van der Waals gas.
+template <class S>
+static bool eos_ok(const Gas& g, const Prim<S>& p) {
+  bool ok = val(p.rho) > 0 && val(p.P) > 0;
+  if (g.kind != 0) ok = ok && 1.0 - g.b * val(p.rho) > 0 && val(p.a2) > 0;
+  return ok;
+}
+
 // The reduction rate: a constant xi (Sec. 4.1), or, with an upper limit
 // C_max of the sound speed, xi = [1 + (a/C_max)^4]^(1/4) evaluated from the
 // local sound speed a of the state at hand (eq. cx, Sec. 4.1 "Functional
@@ -150,7 +221,7 @@ static S xi_at(const Xi<S>& x, const S& a) {
 }
 
 template <class S>
-static Prim<S> primitives(const S* u, int ndim, double gamma, const Xi<S>& xi) {
+static Prim<S> primitives(const S* u, int ndim, const Gas& gas, const Xi<S>& xi) {
   Prim<S> p;
   p.rho = u[0];
   S mv = S(0.0);  // sum_i m_i V_i = rho |V|^2
@@ -161,8 +232,8 @@ static Prim<S> primitives(const S* u, int ndim, double gamma, const Xi<S>& xi) {
     mv = mv + u[1 + d] * p.v[d];
     v2 = v2 + p.v[d] * p.v[d];
   }
-  p.P = (gamma - 1.0) * (u[ndim + 1] - 0.5 * mv);
-  p.a2 = gamma * p.P / p.rho;
+  p.P = eos_P(gas, p.rho, u[ndim + 1] - 0.5 * mv);
+  p.a2 = eos_a2(gas, p.rho, p.P);
   p.a = ssqrt(p.a2);
   p.vabs = ssqrt(v2);
   p.ctot = p.vabs + p.a / xi_at(xi, p.a);
@@ -198,12 +269,12 @@ static S mc_slope(const S& l, const S& r) {
 // along axis d, with the RSST speed c_tot = |V| + a/xi (Sec. 4.1).
 // Returns false if either face state is non-physical.
 template <class S>
-static bool llf_flux(const S* UL, const S* UR, int ndim, int d, double gamma,
+static bool llf_flux(const S* UL, const S* UR, int ndim, int d, const Gas& gas,
                      const Xi<S>& xi, S* Fhat) {
   const int nv = ndim + 2;
-  Prim<S> pl = primitives(UL, ndim, gamma, xi);
-  Prim<S> pr = primitives(UR, ndim, gamma, xi);
-  bool ok = val(pl.rho) > 0 && val(pl.P) > 0 && val(pr.rho) > 0 && val(pr.P) > 0;
+  Prim<S> pl = primitives(UL, ndim, gas, xi);
+  Prim<S> pr = primitives(UR, ndim, gas, xi);
+  bool ok = eos_ok(gas, pl) && eos_ok(gas, pr);
   S FL[5], FR[5];
   euler_flux(UL, pl, ndim, d, FL);
   euler_flux(UR, pr, ndim, d, FR);
@@ -217,25 +288,32 @@ static bool llf_flux(const S* UL, const S* UR, int ndim, int d, double gamma,
 // uncorrected increments D = (Delta rho, Delta m_i, Delta E), plus the
 // external force g (App. B: rho g in momentum, rho V.g in energy, Delta P
 // unchanged).  f = 1 - 1/xi^2.
-//   Delta P = (gamma-1) ( |V|^2/2 Delta rho - V.Delta m + Delta E )      eq. pvs_dt_dpr
+//   Delta P = [(de/dP)_rho]^-1 { [|V|^2/2 - (de/drho)_P] Delta rho
+//             - V.Delta m + Delta E }                                      eq. pvs_dt_dpr
+//           = (gamma-1) ( |V|^2/2 Delta rho - V.Delta m + Delta E )  (ideal gas)
 //   PVS: R = D - f (1/a^2, V/a^2, (E+P)/(rho a^2)) Delta P                eq. pvs_dt, pvs_cons_rhs
 //   PMS: R = D - f (1/a^2, 0, (E+P-rho V^2)/(rho a^2)) Delta P            App. A.2
 //   DVS: R = D - f (1, V, (E+P)/rho) Delta rho                            App. A.1
 //   DMS: R = D - f (1, 0, (E+P-rho V^2)/rho) Delta rho                    App. A.3
-//   PD : R = D - f (0, 0, 1/(gamma-1)) Delta P                            App. A.4
+//   PD : R = D - f (0, 0, (de/dP)_rho) Delta P                            App. A.4
 // (E + P = e + P + rho V^2/2 and E + P - rho V^2 = e + P - rho V^2/2.)
 template <class S>
-static void rsst_correct(const S* u, const S* D, int ndim, double gamma,
+static void rsst_correct(const S* u, const S* D, int ndim, const Gas& gas,
                          const Xi<S>& xi, int form, const double* g, S* R) {
   const int nv = ndim + 2;
-  Prim<S> p = primitives(u, ndim, gamma, xi);
+  const double gamma = gas.gamma;
+  Prim<S> p = primitives(u, ndim, gas, xi);
   const S xc = xi_at(xi, p.a);  // the cell's rate
   S f = 1.0 - 1.0 / (xc * xc);
   S v2 = S(0.0);
   for (int d = 0; d < ndim; ++d) v2 = v2 + p.v[d] * p.v[d];
   S vdm = S(0.0);
   for (int d = 0; d < ndim; ++d) vdm = vdm + p.v[d] * D[1 + d];
-  S dP = (gamma - 1.0) * (0.5 * v2 * D[0] - vdm + D[nv - 1]);
+  S dP;
+  if (gas.kind == 0)
+    dP = (gamma - 1.0) * (0.5 * v2 * D[0] - vdm + D[nv - 1]);
+  else
+    dP = ((0.5 * v2 - eos_dedrho(gas, p.rho, p.P)) * D[0] - vdm + D[nv - 1]) / eos_dedP(gas, p.rho);
   S E = u[nv - 1];
   for (int k = 0; k < nv; ++k) R[k] = D[k];
   switch (form) {
@@ -266,7 +344,8 @@ static void rsst_correct(const S* u, const S* D, int ndim, double gamma,
       break;
     }
     case F_PD: {
-      R[nv - 1] = D[nv - 1] - f * dP / (gamma - 1.0);
+      if (gas.kind == 0) R[nv - 1] = D[nv - 1] - f * dP / (gamma - 1.0);
+      else R[nv - 1] = D[nv - 1] - f * eos_dedP(gas, p.rho) * dP;
       break;
     }
     default:
@@ -287,6 +366,10 @@ struct Grid {
   int ndim, n[3], nv;
   int64_t ncell;
 };
+
+static Gas gas_of(const ora_config* c) {
+  return c->eos == 1 ? Gas{c->gamma, 1, c->eos_a, c->eos_b} : ideal_gas(c->gamma);
+}
 
 static Grid make_grid(const ora_config* c) {
   Grid G;
@@ -348,7 +431,7 @@ static bool face_flux(const Grid& G, const ora_config* c, const S* U, const int 
     UL[v] = ghosted(G, c, U, v, idx) + 0.5 * sl[v];
     UR[v] = ghosted(G, c, U, v, ir) - 0.5 * sr[v];
   }
-  return llf_flux(UL, UR, G.ndim, d, c->gamma, xi, Fhat);
+  return llf_flux(UL, UR, G.ndim, d, gas_of(c), xi, Fhat);
 }
 
 // Full semi-discrete right-hand side R(U) on every cell.
@@ -375,9 +458,10 @@ static int64_t rate_field(const ora_config* c, const S* U, const Xi<S>& xi, S* R
           if (!face_flux(G, c, U, il, d, xi, Fm)) ++bad;
           for (int v = 0; v < nv; ++v) D[v] = D[v] - (Fp[v] - Fm[v]) / c->dx[d];
         }
-        Prim<S> p = primitives(u, G.ndim, c->gamma, xi);
-        if (!(val(p.rho) > 0 && val(p.P) > 0)) ++bad;
-        rsst_correct(u, D, G.ndim, c->gamma, xi, c->form, c->g, Rc);
+        const Gas gas = gas_of(c);
+        Prim<S> p = primitives(u, G.ndim, gas, xi);
+        if (!eos_ok(gas, p)) ++bad;
+        rsst_correct(u, D, G.ndim, gas, xi, c->form, c->g, Rc);
         for (int v = 0; v < nv; ++v) R[(int64_t)v * G.ncell + ci] = Rc[v];
       }
     }
@@ -393,7 +477,7 @@ static double max_ctot(const ora_config* c, const double* U) {
   for (int64_t ci = 0; ci < G.ncell; ++ci) {
     double u[5];
     for (int v = 0; v < G.nv; ++v) u[v] = U[(int64_t)v * G.ncell + ci];
-    Prim<double> p = primitives(u, G.ndim, c->gamma, Xi<double>{c->xi, c->cmax});
+    Prim<double> p = primitives(u, G.ndim, gas_of(c), Xi<double>{c->xi, c->cmax});
     if (p.ctot > cmax) cmax = p.ctot;
   }
   return cmax;
@@ -433,7 +517,7 @@ static int64_t ssp_rk2(const ora_config* c, S* U, const Xi<S>& xi, double dt) {
 
 extern "C" {
 
-int ora_version(void) { return 1; }
+int ora_version(void) { return 2; }
 
 // OpenMP threads the oracle's loops use.
 int ora_threads(void) { return omp_get_max_threads(); }
@@ -443,13 +527,13 @@ void ora_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 
 // Primitive recovery of one cell: out = (rho, V1, V2, V3, P, a2, a, |V|, c_tot)
 void ora_prim(int ndim, double gamma, double xi, double cmax, const double* u, double* out) {
-  Prim<double> p = primitives(u, ndim, gamma, Xi<double>{xi, cmax});
+  Prim<double> p = primitives(u, ndim, ideal_gas(gamma), Xi<double>{xi, cmax});
   out[0] = p.rho; out[1] = p.v[0]; out[2] = p.v[1]; out[3] = p.v[2];
   out[4] = p.P; out[5] = p.a2; out[6] = p.a; out[7] = p.vabs; out[8] = p.ctot;
 }
 
 void ora_flux(int ndim, double gamma, const double* u, int d, double* F) {
-  Prim<double> p = primitives(u, ndim, gamma, Xi<double>{1.0, 0.0});
+  Prim<double> p = primitives(u, ndim, ideal_gas(gamma), Xi<double>{1.0, 0.0});
   euler_flux(u, p, ndim, d, F);
 }
 
@@ -458,7 +542,7 @@ void ora_flux_jacobian(int ndim, double gamma, const double* u, int d, double* J
   const int nv = ndim + 2;
   Dual<5> ud[5];
   for (int k = 0; k < nv; ++k) { ud[k] = Dual<5>(u[k]); ud[k].d[k] = 1.0; }
-  Prim<Dual<5>> p = primitives(ud, ndim, gamma, Xi<Dual<5>>{Dual<5>(1.0), 0.0});
+  Prim<Dual<5>> p = primitives(ud, ndim, ideal_gas(gamma), Xi<Dual<5>>{Dual<5>(1.0), 0.0});
   Dual<5> F[5];
   euler_flux(ud, p, ndim, d, F);
   for (int r = 0; r < nv; ++r)
@@ -469,12 +553,37 @@ double ora_mc(double l, double r) { return mc_slope(l, r); }
 
 int ora_llf(int ndim, double gamma, double xi, const double* UL, const double* UR, int d,
             double* F) {
-  return llf_flux(UL, UR, ndim, d, gamma, Xi<double>{xi, 0.0}, F) ? 0 : 1;
+  return llf_flux(UL, UR, ndim, d, ideal_gas(gamma), Xi<double>{xi, 0.0}, F) ? 0 : 1;
 }
 
 void ora_correct(int ndim, double gamma, double xi, double cmax, int form, const double* u,
                  const double* D, const double* g, double* R) {
-  rsst_correct(u, D, ndim, gamma, Xi<double>{xi, cmax}, form, g, R);
+  rsst_correct(u, D, ndim, ideal_gas(gamma), Xi<double>{xi, cmax}, form, g, R);
+}
+
+// The equation of state at one (rho, P): out = (e(rho, P), P(rho, e) of that
+// e, (de/dP)_rho, (de/drho)_P, a^2).  kind 0 ideal gas, 1 van der Waals.
+void ora_eos(double gamma, int kind, double a, double b, double rho, double P, double* out) {
+  const Gas g{gamma, kind, a, b};
+  const double e = eos_e(g, rho, P);
+  out[0] = e;
+  out[1] = eos_P(g, rho, e);
+  out[2] = eos_dedP(g, rho);
+  out[3] = eos_dedrho(g, rho, P);
+  out[4] = eos_a2(g, rho, P);
+}
+
+// ora_prim and ora_correct for a given equation of state (constant xi).
+void ora_prim_eos(int ndim, double gamma, int kind, double a, double b, double xi,
+                  const double* u, double* out) {
+  Prim<double> p = primitives(u, ndim, Gas{gamma, kind, a, b}, Xi<double>{xi, 0.0});
+  out[0] = p.rho; out[1] = p.v[0]; out[2] = p.v[1]; out[3] = p.v[2];
+  out[4] = p.P; out[5] = p.a2; out[6] = p.a; out[7] = p.vabs; out[8] = p.ctot;
+}
+
+void ora_correct_eos(int ndim, double gamma, int kind, double a, double b, double xi, int form,
+                     const double* u, const double* D, const double* g, double* R) {
+  rsst_correct(u, D, ndim, Gas{gamma, kind, a, b}, Xi<double>{xi, 0.0}, form, g, R);
 }
 
 double ora_cfl_dt(const ora_config* c, const double* U) { return cfl_dt(c, U); }
@@ -545,7 +654,7 @@ void ora_diag(const ora_config* c, const double* U, double* out) {
     double u[5];
     for (int v = 0; v < G.nv; ++v) u[v] = U[(int64_t)v * G.ncell + ci];
     const Xi<double> law{c->xi, c->cmax};
-    Prim<double> p = primitives(u, G.ndim, c->gamma, law);
+    Prim<double> p = primitives(u, G.ndim, gas_of(c), law);
     s[0] += u[0];
     double m2 = 0.0;
     for (int d = 0; d < G.ndim; ++d) { s[1 + d] += u[1 + d]; m2 += u[1 + d] * u[1 + d]; }

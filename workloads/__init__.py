@@ -1,10 +1,11 @@
 """Seeded synthetic inputs for the RSST step (shared by tests, smoke and bench).
 
 This module holds initial conditions only: grids, seeded random draws, and
-the ideal-gas conversion of (rho, V, P) point values at cell centres to the
-conservative state (rho, rho V, E) with E = P/(gamma-1) + rho|V|^2/2.  It
-contains none of the time-step arithmetic, and imports neither the oracle
-nor the GPU library.
+the conversion of (rho, V, P) point values at cell centres to the
+conservative state (rho, rho V, E) with E = e(rho, P) + rho|V|^2/2, e the
+internal energy density of the gas (ideal: P/(gamma-1); or the van der
+Waals gas below).  It contains none of the time-step arithmetic, and imports
+neither the oracle nor the GPU library.
 
 Every field is a float64 numpy array laid out [nvar][nz][ny][nx] (x fastest),
 nvar = ndim + 2, variables (rho, rho V_1..rho V_ndim, E).  A parameter dict
@@ -29,12 +30,48 @@ import numpy as np
 GAMMA = 5.0 / 3.0
 SEED0 = 20181211
 
+# A van der Waals gas for the general equation of state (the paper reports
+# having run such a gas without giving its parameters): attraction a = 0.2
+# and co-volume b = 0.1, in units where rho and P are of order one, so that
+# a rho^2 is a fifth of P and b rho a tenth at rho = P = 1.  Its internal
+# energy density with constant specific heat is
+#   e(rho, P) = (P + a rho^2)(1 - b rho)/(gamma-1) - a rho^2.
+VDW = {"eos": "vdw", "eos_a": 0.2, "eos_b": 0.1}
+
 
 def seed(k: int) -> int:
     return SEED0 + k
 
 
-def conservative(rho, vel, P, gamma=GAMMA) -> np.ndarray:
+def internal_energy(rho, P, gamma=GAMMA, gas=None):
+    """Internal energy density e(rho, P) of the ideal gas (gas None or
+    eos 'ideal') or of a van der Waals gas {eos: 'vdw', eos_a, eos_b}."""
+    P = np.asarray(P, dtype=np.float64)
+    if gas is None or gas.get("eos", "ideal") == "ideal":
+        return P / (gamma - 1.0)
+    a, b = float(gas["eos_a"]), float(gas["eos_b"])
+    return (P + a * rho * rho) * (1.0 - b * rho) / (gamma - 1.0) - a * rho * rho
+
+
+def sound_speed(rho, P, gamma=GAMMA, gas=None):
+    """Sound speed of the same gases, for setting up linear waves: ideal
+    sqrt(gamma P / rho); van der Waals (textbook form)
+    sqrt(gamma (P + a rho^2)/(rho (1 - b rho)) - 2 a rho)."""
+    if gas is None or gas.get("eos", "ideal") == "ideal":
+        return np.sqrt(gamma * P / rho)
+    a, b = float(gas["eos_a"]), float(gas["eos_b"])
+    return np.sqrt(gamma * (P + a * rho * rho) / (rho * (1.0 - b * rho)) - 2.0 * a * rho)
+
+
+def with_gas(cfg: dict, gas) -> dict:
+    """cfg with the equation-of-state keys of gas (None: unchanged)."""
+    if gas is not None:
+        cfg = dict(cfg)
+        cfg.update(gas)
+    return cfg
+
+
+def conservative(rho, vel, P, gamma=GAMMA, gas=None) -> np.ndarray:
     """Stack (rho, rho V_i, E) from point values; vel is a list of arrays."""
     rho = np.asarray(rho, dtype=np.float64)
     comps = [rho]
@@ -43,7 +80,7 @@ def conservative(rho, vel, P, gamma=GAMMA) -> np.ndarray:
         v = np.broadcast_to(np.asarray(v, dtype=np.float64), rho.shape)
         comps.append(rho * v)
         ke = ke + v * v
-    E = np.asarray(P, dtype=np.float64) / (gamma - 1.0) + 0.5 * rho * ke
+    E = internal_energy(rho, P, gamma, gas) + 0.5 * rho * ke
     comps.append(E)
     return np.ascontiguousarray(np.stack(comps))
 
@@ -73,24 +110,25 @@ def centres(cfg: dict, d: int) -> np.ndarray:
 
 # --------------------------------------------------------------- 1D wave
 
-def wave1d(xi=1.0, form="pvs", n=256, eps=1e-4):
+def wave1d(xi=1.0, form="pvs", n=256, eps=1e-4, gas=None):
     """Right-going RSST sound wave plus a static entropy wave, one wavelength.
 
     rho0 = P0 = 1.  Sound: drho = eps sin kx, dP = a0^2 drho,
     dV = xi a0 drho / rho0 (the RSST sound eigenvector: the velocity
     amplitude is xi times the Euler one).  Entropy: drho = eps cos kx.
     Runs to t_end = 2 xi L / a0, two crossings at the reduced speed a0/xi.
+    gas: None (ideal) or a van der Waals gas, whose a0 the wave then uses.
     """
-    cfg = base_cfg(1, [n], xi=xi, form=form)
+    cfg = with_gas(base_cfg(1, [n], xi=xi, form=form), gas)
     x = centres(cfg, 0)
     k = 2 * math.pi
-    a0 = math.sqrt(GAMMA)
+    a0 = float(sound_speed(1.0, 1.0, GAMMA, gas))
     ds = eps * np.sin(k * x)
     de = eps * np.cos(k * x)
     rho = 1.0 + ds + de
     P = 1.0 + a0 * a0 * ds
     V = xi * a0 * ds
-    U = conservative(rho, [V], P)
+    U = conservative(rho, [V], P, gas=gas)
     meta = {"t_end": 2.0 * xi / a0, "a0": a0, "eps": eps, "k": k}
     return cfg, U, meta
 
@@ -140,14 +178,16 @@ def polytrope(z, contrast=100.0, delta=1e-4, g=1.0):
     return rho, rho * T
 
 
-def strat3d(n=256, xi=30.0, form="pvs", nz=None, ny=None):
+def strat3d(n=256, xi=30.0, form="pvs", nz=None, ny=None, gas=None):
     """3D stratified box: polytrope along z (contrast 100, delta 1e-4, g = 1
     along -z), walls in z, periodic in x and y, V = 0, pressure noise
-    P <- P (1 + 1e-3 U(-1,1)).  Background: the unperturbed polytrope."""
+    P <- P (1 + 1e-3 U(-1,1)).  Background: the unperturbed polytrope.
+    gas: a van der Waals gas keeps the same rho and P (hydrostatic balance
+    does not involve the equation of state) with its own E."""
     nz = nz or n
     ny = ny or n
-    cfg = base_cfg(3, [n, ny, nz], xi=xi, form=form,
-                   bc_lo=["periodic", "periodic", "reflect"], g=[0.0, 0.0, -1.0])
+    cfg = with_gas(base_cfg(3, [n, ny, nz], xi=xi, form=form,
+                            bc_lo=["periodic", "periodic", "reflect"], g=[0.0, 0.0, -1.0]), gas)
     z = centres(cfg, 2)
     rho0, P0 = polytrope(z)
     rng = np.random.default_rng(seed(3))
@@ -155,8 +195,8 @@ def strat3d(n=256, xi=30.0, form="pvs", nz=None, ny=None):
     rho = np.broadcast_to(rho0[:, None, None], (nz, ny, n))
     P = P0[:, None, None] * (1.0 + 1e-3 * noise)
     zero = np.zeros((nz, ny, n))
-    U = conservative(rho, [zero, zero, zero], P)
-    bg = conservative(rho0, [np.zeros(nz)] * 3, P0)  # [nv][nz]
+    U = conservative(rho, [zero, zero, zero], P, gas=gas)
+    bg = conservative(rho0, [np.zeros(nz)] * 3, P0, gas=gas)  # [nv][nz]
     return cfg, U, {"bg": bg, "bg_axis": 2}
 
 
@@ -271,12 +311,13 @@ def rt2d(n, form="pvs", xi=6.3, rho1=1.0, rho2=10.0, L=0.025, amp=0.01, Pc=1000.
 # --------------------------------------------------------------- random
 
 def random_state(ndim, n, *, seed_k=100, xi=3.0, form="pvs", bc_lo=None, bc_hi=None,
-                 g=None, mach=0.3, drho=0.5, dP=0.3, white=0.02, length=None):
+                 g=None, mach=0.3, drho=0.5, dP=0.3, white=0.02, length=None, gas=None):
     """Smooth random admissible state plus small white noise (exercises every
     limiter branch).  rho in about [1-drho, 1+drho], P about 1 +- dP, |V|
-    about mach * a."""
+    about mach * a.  gas: None (ideal) or a van der Waals gas."""
     rng = np.random.default_rng(seed(seed_k))
-    cfg = base_cfg(ndim, n, xi=xi, form=form, bc_lo=bc_lo, bc_hi=bc_hi, g=g, length=length)
+    cfg = with_gas(base_cfg(ndim, n, xi=xi, form=form, bc_lo=bc_lo, bc_hi=bc_hi, g=g, length=length),
+                   gas)
     shape = tuple(reversed(list(n)))
     grids = np.meshgrid(*[centres(cfg, d) / (cfg["dx"][d] * cfg["n"][d])
                           for d in reversed(range(ndim))], indexing="ij")
@@ -297,4 +338,4 @@ def random_state(ndim, n, *, seed_k=100, xi=3.0, form="pvs", bc_lo=None, bc_hi=N
     P = 1.0 + dP * smooth()
     a = np.sqrt(GAMMA * P / rho)
     vel = [mach * a * smooth() for _ in range(ndim)]
-    return cfg, conservative(rho, vel, P)
+    return cfg, conservative(rho, vel, P, gas=gas)
