@@ -429,6 +429,19 @@ def main():
                                 "speed_vs_constant_xi": round(ms_step / msc, 3),
                                 "cfl_dt": dtc, "cfl_dt_constant_xi30": dt30}
 
+    # the same 256^3 box as a van der Waals gas (same rho and P, so the same
+    # hydrostatic balance; E from that gas's internal energy): the cost of
+    # the general equation of state in the step
+    cfg_v, U0v, _ = W.strat3d(n=256, xi=30.0, form="pvs", gas=W.VDW)
+    Uv = torch.from_numpy(U0v).to(dev)
+    sv = R.Solver(cfg_v)
+    msv = timed(sv, Uv, K)
+    sv.close()
+    del Uv
+    sec["strat3d_vdw_fp64"] = {"eos": dict(W.VDW), "ms_per_step": round(msv, 5),
+                               "Gcell_updates_s": round(ncell / (msv * 1e-3) / 1e9, 4),
+                               "speed_vs_ideal_gas": round(ms_step / msv, 3)}
+
     # 2D bubble 512^2 FP64 (L2/MALL resident; launch-latency sensitive)
     cfg2, U2_0, meta2 = W.bubble2d()
     U2 = torch.from_numpy(U2_0).to(dev)
@@ -521,6 +534,16 @@ def main():
         s.close()
         out["secondary"]["strat3d_cmax_fp64"]["err_vs_oracle"] = parity_err(Ugc.cpu().numpy(), Uoc, 3)
         out["secondary"]["strat3d_cmax_fp64"]["err_steps"] = 1
+        # van der Waals gas: one step of the 256^3 box against the oracle
+        Uov, _, _ = oracle.run(cfg_v, U0v, 1)
+        Ugv = torch.from_numpy(U0v).to(dev)
+        s = R.Solver(cfg_v)
+        s.step(Ugv)
+        torch.cuda.synchronize()
+        s.close()
+        out["secondary"]["strat3d_vdw_fp64"]["err_vs_oracle"] = parity_err(Ugv.cpu().numpy(), Uov, 3)
+        out["secondary"]["strat3d_vdw_fp64"]["err_steps"] = 1
+        del Ugv, Uov
         # the bubble's FP32 perturbation over 5 steps against the FP64 oracle
         Uo2, _, _ = oracle.run(cfg2, meta2["bg"][:, :, None] + U2p0.astype(np.float64), 5)
         g2 = torch.from_numpy(U2p0).to(dev)

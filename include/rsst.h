@@ -11,7 +11,8 @@
  *   - local Lax-Friedrichs interface flux with c_tot = |V| + a/xi;
  *   - flux divergence Delta rho, Delta(rho V_i), Delta E   (eq. pvs_dt0);
  *   - Delta P from those increments                       (eq. pvs_dt_dpr,
- *     ideal gas: (de/dP)_rho = 1/(gamma-1), (de/drho)_P = 0);
+ *     ideal gas: (de/dP)_rho = 1/(gamma-1), (de/drho)_P = 0; or the
+ *     van der Waals gas of rsst_eos);
  *   - the corrected time derivatives of the chosen form:
  *       PVS (eq. pvs_dt), DVS (App. A.1), PMS (App. A.2), DMS (App. A.3),
  *       PD (App. A.4), or plain Euler;
@@ -85,7 +86,26 @@ typedef struct rsst_config {
                         and f = 1 - 1/xi^2 of every cell's correction.  The
                         field xi is unused.  0: the constant xi.  Not with
                         the batch or the adjoint (RSST_E_UNSUPPORTED).        */
+  int eos;           /* rsst_eos: the equation of state of the gas            */
+  double eos_a;      /* RSST_EOS_VDW: attraction a >= 0 and co-volume b >= 0  */
+  double eos_b;      /* of the van der Waals gas (below); ignored otherwise   */
 } rsst_config;
+
+/* Equation of state (Sec. 3.2; the general form enters through the
+ * thermodynamic derivatives of eq. pvs_cons_therm in Delta P, eq.
+ * pvs_cons_dpr, and through the sound speed in c_tot and the correction).
+ *   RSST_EOS_IDEAL: e = P/(gamma-1).
+ *   RSST_EOS_VDW:   van der Waals gas with constant specific heat,
+ *                   e = (P + a rho^2)(1 - b rho)/(gamma-1) - a rho^2,
+ *                   so P = (gamma-1)(e + a rho^2)/(1 - b rho) - a rho^2 and
+ *                   a_s^2 = gamma (P + a rho^2)/(rho (1 - b rho)) - 2 a rho.
+ *                   e is the internal energy per unit volume, E - rho|V|^2/2.
+ *                   FP64 storage with constant xi only (RSST_E_UNSUPPORTED
+ *                   with RSST_FP32_PERT, cmax > 0 or RSST_WITH_ADJOINT; the
+ *                   batch takes ideal-gas boxes only).  A cell with
+ *                   b rho >= 1 is flagged like rho <= 0, one with
+ *                   a_s^2 <= 0 like P <= 0. */
+enum rsst_eos { RSST_EOS_IDEAL = 0, RSST_EOS_VDW = 1 };
 
 enum rsst_flag {
   RSST_WITH_ADJOINT = 1  /* rsst_init also reserves the workspace of

@@ -53,6 +53,7 @@ class _Config(ctypes.Structure):
         ("eos", ctypes.c_int),
         ("eos_a", ctypes.c_double),
         ("eos_b", ctypes.c_double),
+        ("p_probe", ctypes.c_double),
     ]
 
 
@@ -143,6 +144,7 @@ def make_config(cfg: dict) -> _Config:
     c.eos = EOS[e] if isinstance(e, str) else int(e)
     c.eos_a = float(cfg.get("eos_a", 0.0))
     c.eos_b = float(cfg.get("eos_b", 0.0))
+    c.p_probe = float(cfg.get("p_probe", 0.0))
     return c
 
 

@@ -72,6 +72,9 @@ typedef struct {
   int eos;         // 0 ideal gas, 1 van der Waals gas (eos_a, eos_b)
   double eos_a;    // van der Waals attraction a
   double eos_b;    // van der Waals co-volume b
+  double p_probe;  // 0, or a relative change applied to every pressure the
+                   // run evaluates: measures how much a run amplifies a
+                   // one-ulp difference in the equation of state (tests only)
 } ora_config;
 
 }  // extern "C"
@@ -147,9 +150,10 @@ struct Gas {
   double gamma;
   int kind;
   double a, b;
+  double probe;  // relative change of every pressure evaluation (0: none)
 };
 
-static inline Gas ideal_gas(double gamma) { return Gas{gamma, 0, 0.0, 0.0}; }
+static inline Gas ideal_gas(double gamma) { return Gas{gamma, 0, 0.0, 0.0, 0.0}; }
 
 // Internal energy density e(rho, P).
 template <class S>
@@ -233,6 +237,7 @@ static Prim<S> primitives(const S* u, int ndim, const Gas& gas, const Xi<S>& xi)
     v2 = v2 + p.v[d] * p.v[d];
   }
   p.P = eos_P(gas, p.rho, u[ndim + 1] - 0.5 * mv);
+  if (gas.probe != 0.0) p.P = p.P * (1.0 + gas.probe);
   p.a2 = eos_a2(gas, p.rho, p.P);
   p.a = ssqrt(p.a2);
   p.vabs = ssqrt(v2);
@@ -368,7 +373,9 @@ struct Grid {
 };
 
 static Gas gas_of(const ora_config* c) {
-  return c->eos == 1 ? Gas{c->gamma, 1, c->eos_a, c->eos_b} : ideal_gas(c->gamma);
+  Gas g = c->eos == 1 ? Gas{c->gamma, 1, c->eos_a, c->eos_b, 0.0} : ideal_gas(c->gamma);
+  g.probe = c->p_probe;
+  return g;
 }
 
 static Grid make_grid(const ora_config* c) {
@@ -564,7 +571,7 @@ void ora_correct(int ndim, double gamma, double xi, double cmax, int form, const
 // The equation of state at one (rho, P): out = (e(rho, P), P(rho, e) of that
 // e, (de/dP)_rho, (de/drho)_P, a^2).  kind 0 ideal gas, 1 van der Waals.
 void ora_eos(double gamma, int kind, double a, double b, double rho, double P, double* out) {
-  const Gas g{gamma, kind, a, b};
+  const Gas g{gamma, kind, a, b, 0.0};
   const double e = eos_e(g, rho, P);
   out[0] = e;
   out[1] = eos_P(g, rho, e);
@@ -576,14 +583,14 @@ void ora_eos(double gamma, int kind, double a, double b, double rho, double P, d
 // ora_prim and ora_correct for a given equation of state (constant xi).
 void ora_prim_eos(int ndim, double gamma, int kind, double a, double b, double xi,
                   const double* u, double* out) {
-  Prim<double> p = primitives(u, ndim, Gas{gamma, kind, a, b}, Xi<double>{xi, 0.0});
+  Prim<double> p = primitives(u, ndim, Gas{gamma, kind, a, b, 0.0}, Xi<double>{xi, 0.0});
   out[0] = p.rho; out[1] = p.v[0]; out[2] = p.v[1]; out[3] = p.v[2];
   out[4] = p.P; out[5] = p.a2; out[6] = p.a; out[7] = p.vabs; out[8] = p.ctot;
 }
 
 void ora_correct_eos(int ndim, double gamma, int kind, double a, double b, double xi, int form,
                      const double* u, const double* D, const double* g, double* R) {
-  rsst_correct(u, D, ndim, Gas{gamma, kind, a, b}, Xi<double>{xi, 0.0}, form, g, R);
+  rsst_correct(u, D, ndim, Gas{gamma, kind, a, b, 0.0}, Xi<double>{xi, 0.0}, form, g, R);
 }
 
 double ora_cfl_dt(const ora_config* c, const double* U) { return cfl_dt(c, U); }

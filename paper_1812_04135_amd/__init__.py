@@ -21,6 +21,7 @@ RSST_E_NONPHYSICAL = -5
 FORMS = {"euler": 0, "pvs": 1, "pms": 2, "dvs": 3, "dms": 4, "pd": 5}
 BCS = {"periodic": 0, "reflect": 1}
 PRECS = {"fp64": 0, "fp32_pert": 1}
+EOS = {"ideal": 0, "vdw": 1}
 RSST_WITH_ADJOINT = 1
 
 
@@ -43,6 +44,9 @@ class rsst_config(ctypes.Structure):
         ("t_end", ctypes.c_double),
         ("flags", ctypes.c_int),
         ("cmax", ctypes.c_double),
+        ("eos", ctypes.c_int),
+        ("eos_a", ctypes.c_double),
+        ("eos_b", ctypes.c_double),
     ]
 
 
@@ -145,6 +149,10 @@ def make_config(cfg: dict, prec: str = "fp64", bg=None, bg_axis: int = -1,
     c.t_end = float(t_end)
     c.flags = RSST_WITH_ADJOINT if adjoint else 0
     c.cmax = float(cfg.get("cmax", 0.0))
+    e = cfg.get("eos", "ideal")
+    c.eos = EOS[e] if isinstance(e, str) else int(e)
+    c.eos_a = float(cfg.get("eos_a", 0.0))
+    c.eos_b = float(cfg.get("eos_b", 0.0))
     return c
 
 

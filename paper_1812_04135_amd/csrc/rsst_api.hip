@@ -66,6 +66,13 @@ static int validate(const rsst_config* c) {
   if (!(c->cmax >= 0.0) || !std::isfinite(c->cmax)) return RSST_E_ARG;
   if ((c->flags & RSST_WITH_ADJOINT) && c->cmax > 0.0) return RSST_E_UNSUPPORTED;
   if ((c->flags & RSST_WITH_ADJOINT) && c->prec != RSST_FP64) return RSST_E_UNSUPPORTED;
+  if (c->eos != RSST_EOS_IDEAL && c->eos != RSST_EOS_VDW) return RSST_E_ARG;
+  if (c->eos == RSST_EOS_VDW) {
+    if (!(c->eos_a >= 0.0) || !std::isfinite(c->eos_a)) return RSST_E_ARG;
+    if (!(c->eos_b >= 0.0) || !std::isfinite(c->eos_b)) return RSST_E_ARG;
+    if (c->prec != RSST_FP64 || c->cmax > 0.0 || (c->flags & RSST_WITH_ADJOINT))
+      return RSST_E_UNSUPPORTED;
+  }
   // fields are addressed with 32-bit byte offsets
   {
     const long long cells = (long long)c->n[0] * c->n[1] * c->n[2];
@@ -95,7 +102,7 @@ const char* rsst_strerror(int s) {
   }
 }
 
-const char* rsst_version(void) { return "rsst-gfx950 stage-v6"; }
+const char* rsst_version(void) { return "rsst-gfx950 stage-v7"; }
 
 int rsst_init(const rsst_config* cfg, void* stream, rsst_handle* out) {
   if (!out) return RSST_E_ARG;
@@ -128,6 +135,9 @@ int rsst_init(const rsst_config* cfg, void* stream, rsst_handle* out) {
   a.inv_xi = 1.0 / cfg->xi;
   a.f = 1.0 - 1.0 / (cfg->xi * cfg->xi);
   a.inv_cmax2 = cfg->cmax > 0.0 ? 1.0 / (cfg->cmax * cfg->cmax) : 0.0;
+  a.eos = cfg->eos;
+  a.vdw_a = cfg->eos == RSST_EOS_VDW ? cfg->eos_a : 0.0;
+  a.vdw_b = cfg->eos == RSST_EOS_VDW ? cfg->eos_b : 0.0;
   a.form = cfg->form;
   double hlen;
   if (cfg->dt_rule == 1) {

@@ -261,7 +261,7 @@ static int batch_validate(const rsst_config* c, int nbox, const int64_t* off) {
     if (k.form != c[0].form || k.prec != c[0].prec) return RSST_E_UNSUPPORTED;
     if (k.form < RSST_EULER || k.form > RSST_PD) return RSST_E_ARG;
     if (k.prec == RSST_FP32_PERT && (!k.bg || (k.bg_axis != -1 && k.bg_axis != 1))) return RSST_E_ARG;
-    if (k.t_end != 0.0 || k.cmax != 0.0 || k.flags != 0) return RSST_E_UNSUPPORTED;
+    if (k.t_end != 0.0 || k.cmax != 0.0 || k.flags != 0 || k.eos != RSST_EOS_IDEAL) return RSST_E_UNSUPPORTED;
     if (off[b] < 0) return RSST_E_ARG;
     const long long bytes = 4ll * k.n[0] * k.n[1] * (k.prec == RSST_FP32_PERT ? 4 : 8);
     if (bytes >= (1ll << 31)) return RSST_E_UNSUPPORTED;

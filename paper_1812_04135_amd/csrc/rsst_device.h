@@ -28,7 +28,14 @@ struct Consts {
   double inv_xi;  // 1 / xi
   double f;       // 1 - 1/xi^2
   double inv_cmax2;  // 1/C_max^2 when xi follows the sound speed (eq. cx), else 0
+  double vdw_a;   // van der Waals attraction a (kExtVdw kernels only)
+  double vdw_b;   // van der Waals co-volume b
 };
+
+// Extension bits of a kernel's template argument, above the form (0..5):
+// xi from the sound speed (eq. cx), and the van der Waals equation of state
+// in place of the ideal gas.
+enum Ext { kExtCmax = 8, kExtVdw = 16 };
 
 // A reconstructed face state: conservative values plus the primitive
 // quantities the LLF flux needs.  `vn` is the velocity normal to the face.
@@ -99,10 +106,32 @@ __device__ __forceinline__ double f_cmax(double a2, const Consts& K) {
   return r4 * (y * y) * rcp(1.0 + y);
 }
 
+// Gas pressure P and squared sound speed a^2 from rho, 1/rho and the internal
+// energy density e = E - rho|V|^2/2 (Sec. 3.2).  Ideal gas: P = (gamma-1) e,
+// a^2 = gamma P / rho.  Van der Waals gas with constant specific heat
+// (kExtVdw), e = (P + a rho^2)(1 - b rho)/(gamma-1) - a rho^2, solved for P:
+//   P = (gamma-1)(e + a rho^2)/(1 - b rho) - a rho^2,
+//   a^2 = gamma (P + a rho^2) / (rho (1 - b rho)) - 2 a rho,
+// the isentropic (dP/drho)_S of that gas.  The thermodynamic derivatives of
+// eq. pvs_cons_therm give the same a^2; the oracle takes it from there.
+template <int X>
+__device__ __forceinline__ void eos_pa2(double rho, double ri, double e, const Consts& K, double& P,
+                                        double& a2) {
+  if constexpr ((X & kExtVdw) != 0) {
+    const double q = K.vdw_a * rho * rho;
+    const double r1 = rcp(fma(-K.vdw_b, rho, 1.0));
+    P = fma(K.gm1 * (e + q), r1, -q);
+    a2 = fma(K.gamma * (P + q), ri * r1, -2.0 * K.vdw_a * rho);
+  } else {
+    P = K.gm1 * e;
+    a2 = K.gamma * P * ri;
+  }
+}
+
 // Primitive recovery of a face state, normal axis D (Sec. 3.2 and 4.1):
-// V = m/rho, P = (gamma-1)(E - rho|V|^2/2), c_tot = |V| + sqrt(gamma P/rho)/xi
-// (XCM: xi from eq. cx).
-template <int NDIM, int D, bool XCM = false>
+// V = m/rho, P and a^2 from the equation of state, c_tot = |V| + a/xi
+// (kExtCmax: xi from eq. cx).
+template <int NDIM, int D, int X = 0>
 __device__ __forceinline__ void face_prims(Face<NDIM + 2>& s, const Consts& K) {
   constexpr int NV = NDIM + 2;
   const double ri = rcp(s.u[0]);
@@ -113,19 +142,20 @@ __device__ __forceinline__ void face_prims(Face<NDIM + 2>& s, const Consts& K) {
     v2 = fma(ve, ve, v2);
     if (e == D) vn = ve;
   }
-  s.P = K.gm1 * fma(-0.5 * s.u[0], v2, s.u[NV - 1]);
-  if constexpr (XCM) s.c = sqrt_nr(v2) + a_eff_cmax(K.gamma * s.P * ri, K);
-  else s.c = fma(sqrt_nr(K.gamma * s.P * ri), K.inv_xi, sqrt_nr(v2));
+  double a2;
+  eos_pa2<X>(s.u[0], ri, fma(-0.5 * s.u[0], v2, s.u[NV - 1]), K, s.P, a2);
+  if constexpr ((X & kExtCmax) != 0) s.c = sqrt_nr(v2) + a_eff_cmax(a2, K);
+  else s.c = fma(sqrt_nr(a2), K.inv_xi, sqrt_nr(v2));
   s.vn = vn;
 }
 
 // Face state U + h (h: half slopes, signed) and its primitives.
-template <int NDIM, int D, bool XCM = false>
+template <int NDIM, int D, int X = 0>
 __device__ __forceinline__ void make_face(const double (&u)[NDIM + 2], const double (&h)[NDIM + 2],
                                           bool plus, const Consts& K, Face<NDIM + 2>& s) {
 #pragma unroll
   for (int v = 0; v < NDIM + 2; ++v) s.u[v] = plus ? u[v] + h[v] : u[v] - h[v];
-  face_prims<NDIM, D, XCM>(s, K);
+  face_prims<NDIM, D, X>(s, K);
 }
 
 // Twice the local Lax-Friedrichs flux between left state L and right state
@@ -161,12 +191,14 @@ __device__ __forceinline__ Face<NDIM + 2> mirror(const Face<NDIM + 2>& s) {
 // Corrected time derivative of one cell (eq. pvs_dt, pvs_dt_dpr; App. A.1-A.4)
 // plus the external force (App. B).  u: stage-input cell state; Dl: the
 // uncorrected increments (Delta rho, Delta m_i, Delta E).  Returns the
-// non-physical flags of the cell.  XCM: f from the cell's own xi (eq. cx).
-template <int NDIM, int FORM, bool XCM = false>
+// non-physical flags of the cell.  kExtCmax: f from the cell's own xi
+// (eq. cx); kExtVdw: the van der Waals gas of eos_pa2.
+template <int NDIM, int FORM, int X = 0>
 __device__ __forceinline__ unsigned rsst_rate(const double (&u)[NDIM + 2], const double (&Dl)[NDIM + 2],
                                               const Consts& K, const double (&g)[3],
                                               double (&R)[NDIM + 2]) {
   constexpr int NV = NDIM + 2;
+  constexpr bool VDW = (X & kExtVdw) != 0;
   const double rho = u[0];
   const double ri = rcp(rho);
   double v[NDIM];
@@ -177,21 +209,33 @@ __device__ __forceinline__ unsigned rsst_rate(const double (&u)[NDIM + 2], const
     v2 = fma(v[e], v[e], v2);
     vdm = fma(v[e], Dl[1 + e], vdm);
   }
-  const double P = K.gm1 * fma(-0.5 * rho, v2, u[NV - 1]);
+  double P, a2;
+  eos_pa2<X>(rho, ri, fma(-0.5 * rho, v2, u[NV - 1]), K, P, a2);
+  // van der Waals: 1 - b rho, the factor of (de/dP)_rho = (1 - b rho)/(gamma-1)
+  const double omb = VDW ? fma(-K.vdw_b, rho, 1.0) : 1.0;
   unsigned bad = 0;
-  if (!(rho > 0.0)) bad |= kBadRho;
-  if (!(P > 0.0)) bad |= kBadP;
+  if (!(rho > 0.0) || !(omb > 0.0)) bad |= kBadRho;
+  if (!(P > 0.0) || (VDW && !(a2 > 0.0))) bad |= kBadP;
   if (!(fabs(u[NV - 1]) < INFINITY) || !(fabs(P) < INFINITY)) bad |= kNonFinite;
 #pragma unroll
   for (int q = 0; q < NV; ++q) R[q] = Dl[q];
   if constexpr (FORM != kEuler) {
-    const double f = XCM ? f_cmax(K.gamma * P * ri, K) : K.f;
-    // Delta P = (gamma-1) (|V|^2/2 Delta rho - V.Delta m + Delta E)
-    const double dP = K.gm1 * (fma(0.5 * v2, Dl[0], Dl[NV - 1]) - vdm);
+    const double f = (X & kExtCmax) ? f_cmax(a2, K) : K.f;
+    // Delta P = [(de/dP)_rho]^-1 {[|V|^2/2 - (de/drho)_P] Delta rho - V.Delta m + Delta E};
+    // ideal gas: (gamma-1) (|V|^2/2 Delta rho - V.Delta m + Delta E)
+    double dP;
+    if constexpr (VDW) {
+      // (de/drho)_P = [2 a rho (1 - b rho) - b (P + a rho^2)]/(gamma-1) - 2 a rho
+      const double ar2 = 2.0 * K.vdw_a * rho;
+      const double dedr = fma(K.inv_gm1, fma(ar2, omb, -K.vdw_b * fma(K.vdw_a * rho, rho, P)), -ar2);
+      dP = K.gm1 * rcp(omb) * (fma(fma(0.5, v2, -dedr), Dl[0], Dl[NV - 1]) - vdm);
+    } else {
+      dP = K.gm1 * (fma(0.5 * v2, Dl[0], Dl[NV - 1]) - vdm);
+    }
     const double H = (u[NV - 1] + P) * ri;  // (E + P)/rho
     if constexpr (FORM == kPVS || FORM == kPMS) {
-      // s = f Delta P / a^2, a^2 = gamma P / rho
-      const double s = f * dP * rho * rcp(K.gamma * P);
+      // s = f Delta P / a^2 (ideal gas: a^2 = gamma P / rho)
+      const double s = VDW ? f * dP * rcp(a2) : f * dP * rho * rcp(K.gamma * P);
       R[0] -= s;
       if constexpr (FORM == kPVS) {
 #pragma unroll
@@ -211,7 +255,7 @@ __device__ __forceinline__ unsigned rsst_rate(const double (&u)[NDIM + 2], const
         R[NV - 1] = fma(-(H - v2), s, R[NV - 1]);
       }
     } else {  // PD: energy only, (de/dP)_rho Delta P
-      R[NV - 1] = fma(-f * K.inv_gm1, dP, R[NV - 1]);
+      R[NV - 1] = fma(-f * (VDW ? omb * K.inv_gm1 : K.inv_gm1), dP, R[NV - 1]);
     }
   }
 #pragma unroll
@@ -223,7 +267,7 @@ __device__ __forceinline__ unsigned rsst_rate(const double (&u)[NDIM + 2], const
 }
 
 // c_tot of a cell state (for the CFL time step).
-template <int NDIM, bool XCM = false>
+template <int NDIM, int X = 0>
 __device__ __forceinline__ double cell_ctot(const double (&u)[NDIM + 2], const Consts& K) {
   constexpr int NV = NDIM + 2;
   const double ri = rcp(u[0]);
@@ -233,9 +277,10 @@ __device__ __forceinline__ double cell_ctot(const double (&u)[NDIM + 2], const C
     const double ve = u[1 + e] * ri;
     v2 = fma(ve, ve, v2);
   }
-  const double P = K.gm1 * fma(-0.5 * u[0], v2, u[NV - 1]);
-  if constexpr (XCM) return sqrt_nr(v2) + a_eff_cmax(K.gamma * P * ri, K);
-  else return fma(sqrt_nr(K.gamma * P * ri), K.inv_xi, sqrt_nr(v2));
+  double P, a2;
+  eos_pa2<X>(u[0], ri, fma(-0.5 * u[0], v2, u[NV - 1]), K, P, a2);
+  if constexpr ((X & kExtCmax) != 0) return sqrt_nr(v2) + a_eff_cmax(a2, K);
+  else return fma(sqrt_nr(a2), K.inv_xi, sqrt_nr(v2));
 }
 
 // ---- cross-lane moves (wave64 DPP) -------------------------------------

@@ -30,6 +30,8 @@ struct StageArgs {
   double inv_dx[3];
   double gamma, gm1, inv_gm1, inv_xi, f;
   double inv_cmax2;  // > 0: xi = [1 + (a/C_max)^4]^(1/4) per state (eq. cx)
+  int eos;           // 0 ideal gas, 1 van der Waals (a, b below)
+  double vdw_a, vdw_b;
   double g[3];
   int form;
   double dt_fixed;   // > 0: use it, else scal[kDtCur]

@@ -41,7 +41,7 @@ template <int NDIM, typename ST>
 __global__ void __launch_bounds__(256) prime_kernel(const StageArgs A, const ST* __restrict__ u,
                                                     double t0, int set_t) {
   constexpr int NV = NDIM + 2;
-  const Consts K{A.gamma, A.gm1, A.inv_gm1, A.inv_xi, A.f, A.inv_cmax2};
+  const Consts K{A.gamma, A.gm1, A.inv_gm1, A.inv_xi, A.f, A.inv_cmax2, A.vdw_a, A.vdw_b};
   const Geometry& G = A.geo;
   __shared__ double red[4];
   double cm = 0.0;
@@ -63,7 +63,8 @@ __global__ void __launch_bounds__(256) prime_kernel(const StageArgs A, const ST*
 #pragma unroll
       for (int v = 0; v < NV; ++v) q[v] += A.bg[v * A.nbg + b];
     }
-    const double ct = A.inv_cmax2 > 0.0 ? cell_ctot<NDIM, true>(q, K) : cell_ctot<NDIM>(q, K);
+    const double ct = A.eos ? cell_ctot<NDIM, kExtVdw>(q, K)
+                      : (A.inv_cmax2 > 0.0 ? cell_ctot<NDIM, kExtCmax>(q, K) : cell_ctot<NDIM>(q, K));
     if (!(q[0] > 0.0)) bad |= kBadRho;
     if (!(ct < INFINITY)) bad |= kNonFinite;
     cm = fmax(cm, ct);
@@ -104,7 +105,7 @@ __global__ void __launch_bounds__(kDiagThreads) diag_partial_kernel(const StageA
                                                                     const ST* __restrict__ u,
                                                                     double* __restrict__ part) {
   constexpr int NV = NDIM + 2;
-  const Consts K{A.gamma, A.gm1, A.inv_gm1, A.inv_xi, A.f, A.inv_cmax2};
+  const Consts K{A.gamma, A.gm1, A.inv_gm1, A.inv_xi, A.f, A.inv_cmax2, A.vdw_a, A.vdw_b};
   const Geometry& G = A.geo;
   __shared__ double s[8][kDiagThreads];
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -137,8 +138,9 @@ __global__ void __launch_bounds__(kDiagThreads) diag_partial_kernel(const StageA
     acc[5] += 0.5 * m2 * rinv;
     mv = m2 * rinv;
     const double v = sqrt(m2) * rinv;
-    const double P = K.gm1 * (q[NV - 1] - 0.5 * mv);
-    const double a2 = K.gamma * P * rinv;
+    double P, a2;
+    if (A.eos) eos_pa2<kExtVdw>(q[0], rinv, q[NV - 1] - 0.5 * mv, K, P, a2);
+    else eos_pa2<0>(q[0], rinv, q[NV - 1] - 0.5 * mv, K, P, a2);
     const double ae = A.inv_cmax2 > 0.0 ? a_eff_cmax(a2, K) : sqrt(a2) * A.inv_xi;  // a / xi
     acc[6] = fmax(acc[6], v);
     acc[7] = fmax(acc[7], v / ae);

@@ -224,7 +224,7 @@ template <int NDIM, int STAGE, typename ST, int FORMX, int NWXC>
 __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, int tile_s,
                                              int chunk_base, double dt, unsigned& bad) {
   constexpr int FORM = FORMX & 7;     // correction form
-  constexpr bool XCM = (FORMX & 8) != 0;  // xi from the sound speed (eq. cx)
+  constexpr int EXT = FORMX & (kExtCmax | kExtVdw);  // xi from eq. cx; van der Waals gas
   constexpr int NV = NDIM + 2;
   constexpr int PL = NV + 3;          // face payload: U, P, c_tot, V_normal
   constexpr bool HS = (NDIM == 3);    // stacked y rows
@@ -294,7 +294,7 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
     if (!bg_on_m) load_bg<NV>(bgr, A.nbg, ib, bgA);
   }
 
-  const Consts K{A.gamma, A.gm1, A.inv_gm1, A.inv_xi, A.f, A.inv_cmax2};
+  const Consts K{A.gamma, A.gm1, A.inv_gm1, A.inv_xi, A.f, A.inv_cmax2, A.vdw_a, A.vdw_b};
   const double g[3] = {A.g[0], A.g[1], A.g[2]};
   const double hx = 0.5 * A.inv_dx[0], hy = 0.5 * A.inv_dx[1], hz = 0.5 * A.inv_dx[DM];
   const __amdgpu_buffer_rsrc_t uin = field_rsrc(A.uin, fbytes);
@@ -353,8 +353,8 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
       sm0[v] = mc_half(q0[v] - qb[v], q1[v] - q0[v]);
     }
     Face<NV> fl, fr;
-    make_face<NDIM, DM, XCM>(qb, ha, true, K, fl);
-    make_face<NDIM, DM, XCM>(q0, sm0, false, K, fr);
+    make_face<NDIM, DM, EXT>(qb, ha, true, K, fl);
+    make_face<NDIM, DM, EXT>(q0, sm0, false, K, fr);
     flux2<NDIM, DM>(fl, fr, Fm_lo);
   } else {
     load_cell<NDIM, ST>(A, uin, 0, col, -1, bgi_xy, q0);
@@ -452,8 +452,8 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
 #pragma unroll
       for (int v = 0; v < NV; ++v) h[v] = mc_half(q0[v] - uL[v], uR[v] - q0[v]);
       Face<NV> fm, fp;
-      make_face<NDIM, 0, XCM>(q0, h, false, K, fm);
-      make_face<NDIM, 0, XCM>(q0, h, true, K, fp);
+      make_face<NDIM, 0, EXT>(q0, h, false, K, fm);
+      make_face<NDIM, 0, EXT>(q0, h, true, K, fp);
       // the wave-edge faces are redone after the barrier from the seams
       if (!wave_idle) {
         if (lane == 0) put_face(seamM + (row * nwx + wx) * PL, 1, fm);
@@ -494,7 +494,7 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
       for (int v = 0; v < NV; ++v) h[v] = mc_half(q0[v] - uD[v], uU[v] - q0[v]);
       {
         Face<NV> fyp;
-        make_face<NDIM, 1, XCM>(q0, h, true, K, fyp);
+        make_face<NDIM, 1, EXT>(q0, h, true, K, fyp);
         if (row < ts_eff - 1) put_face(Prow + row * nxp + i_raw, PS, fyp);
         if (last_row) {
           // minus state of the row above the tile, and the flux at the
@@ -514,13 +514,13 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
 #pragma unroll
           for (int v = 0; v < NV; ++v) hh[v] = mc_half(uU[v] - q0[v], u2[v] - uU[v]);
           Face<NV> fh;
-          make_face<NDIM, 1, XCM>(uU, hh, false, K, fh);
+          make_face<NDIM, 1, EXT>(uU, hh, false, K, fh);
           flux2<NDIM, 1>(fyp, fh, Fh);
 #pragma unroll
           for (int v = 0; v < NV; ++v) Frow[(v * 2 + 1) * nxp + i_raw] = Fh[v];
         }
       }
-      make_face<NDIM, 1, XCM>(q0, h, false, K, fym);
+      make_face<NDIM, 1, EXT>(q0, h, false, K, fym);
       if (row >= 1) put_face(Mrow + (row - 1) * nxp + i_raw, PS, fym);
       if (first_row) {
         // plus state of the row below the tile, and the flux at the tile's
@@ -535,7 +535,7 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
 #pragma unroll
         for (int v = 0; v < NV; ++v) hh[v] = mc_half(uD[v] - u2[v], q0[v] - uD[v]);
         Face<NV> fh;
-        make_face<NDIM, 1, XCM>(uD, hh, true, K, fh);
+        make_face<NDIM, 1, EXT>(uD, hh, true, K, fh);
         flux2<NDIM, 1>(fh, fym, Fh);
 #pragma unroll
         for (int v = 0; v < NV; ++v) Frow[(v * 2) * nxp + i_raw] = Fh[v];
@@ -624,8 +624,8 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
 #pragma unroll
       for (int v = 0; v < NV; ++v) sm1[v] = mc_half(q1[v] - q0[v], q2[v] - q1[v]);
       Face<NV> fl, fr;
-      make_face<NDIM, DM, XCM>(q0, sm0, true, K, fl);
-      make_face<NDIM, DM, XCM>(q1, sm1, false, K, fr);
+      make_face<NDIM, DM, EXT>(q0, sm0, true, K, fl);
+      make_face<NDIM, DM, EXT>(q1, sm1, false, K, fr);
       flux2<NDIM, DM>(fl, fr, Fm_hi);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
@@ -635,7 +635,7 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
       }
     }
     double R[NV];
-    const unsigned b = rsst_rate<NDIM, FORM, XCM>(q0, Dl, K, g, R);
+    const unsigned b = rsst_rate<NDIM, FORM, EXT>(q0, Dl, K, g, R);
     double un[NV];
     if constexpr (STAGE == 2) {
       if constexpr (F32) finish_cell_bgv<NDIM, ST>(unr, -1, bgA, un);
@@ -654,7 +654,7 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
         buf_store<ST>(uout, col, koff + v * vstride, st);
         out[v] = (double)st + bgv;
       }
-      if constexpr (STAGE == 2) cmax = fmax(cmax, cell_ctot<NDIM, XCM>(out, K));
+      if constexpr (STAGE == 2) cmax = fmax(cmax, cell_ctot<NDIM, EXT>(out, K));
     }
     if constexpr (HM) {
 #pragma unroll

@@ -15,7 +15,8 @@
 
 namespace rsstk {
 
-// FORM: the correction form, plus 8 when xi follows the sound speed (eq. cx).
+// FORM: the correction form, plus kExtCmax when xi follows the sound speed
+// (eq. cx) or kExtVdw for the van der Waals gas.
 #ifndef RSST_LB3
 #define RSST_LB3 512
 #endif
@@ -87,9 +88,16 @@ static hipError_t launch_stage_x(const StageArgs& a, hipStream_t s) {
   }
 }
 
+// The van der Waals kernels exist for FP64 storage only (the C ABI rejects
+// the other combinations before any launch).
 template <int NDIM, int STAGE, typename ST>
 static hipError_t launch_stage_f(const StageArgs& a, hipStream_t s) {
-  return a.inv_cmax2 > 0.0 ? launch_stage_x<NDIM, STAGE, ST, 8>(a, s) : launch_stage_x<NDIM, STAGE, ST, 0>(a, s);
+  if constexpr (sizeof(ST) == 8) {
+    if (a.eos) return launch_stage_x<NDIM, STAGE, ST, kExtVdw>(a, s);
+  }
+  if (a.eos) return hipErrorInvalidValue;
+  return a.inv_cmax2 > 0.0 ? launch_stage_x<NDIM, STAGE, ST, kExtCmax>(a, s)
+                           : launch_stage_x<NDIM, STAGE, ST, 0>(a, s);
 }
 
 template <int NDIM, typename ST>

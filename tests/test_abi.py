@@ -55,6 +55,9 @@ def _bad_configs():
     yield "form", dict(cfg, form=9)
     yield "bc mix", dict(cfg, bc_lo=["periodic", "reflect"], bc_hi=["periodic", "periodic"])
     yield "dt_rule", dict(cfg, dt_rule=3)
+    yield "eos kind", dict(cfg, eos=2)
+    yield "eos a", dict(cfg, eos="vdw", eos_a=-0.1, eos_b=0.1)
+    yield "eos b", dict(cfg, eos="vdw", eos_a=0.1, eos_b=float("nan"))
 
 
 @pytest.mark.parametrize("name,cfg", list(_bad_configs()))
@@ -97,6 +100,21 @@ def test_adjoint_flags_validated_on_host():
     # the adjoint is FP64 only
     c = R.make_config(cfg, prec="fp32_pert", bg=None, adjoint=True)
     c.bg = ctypes.c_void_p(8)  # never dereferenced: rejected before any device call
+    assert R.lib().rsst_init(ctypes.byref(c), None, ctypes.byref(h)) == -4
+    assert not h.value
+
+
+def test_vdw_combinations_unsupported_on_host():
+    """The van der Waals gas runs FP64 storage with a constant xi, without the
+    adjoint; the other combinations are reported before any device call."""
+    cfg, _ = W.random_state(2, [16, 12], gas=W.VDW)
+    h = ctypes.c_void_p()
+    c = R.make_config(cfg, prec="fp32_pert", bg=None)
+    c.bg = ctypes.c_void_p(8)  # never dereferenced
+    assert R.lib().rsst_init(ctypes.byref(c), None, ctypes.byref(h)) == -4
+    c = R.make_config(dict(cfg, cmax=5.0))
+    assert R.lib().rsst_init(ctypes.byref(c), None, ctypes.byref(h)) == -4
+    c = R.make_config(cfg, adjoint=True)
     assert R.lib().rsst_init(ctypes.byref(c), None, ctypes.byref(h)) == -4
     assert not h.value
 

@@ -165,3 +165,10 @@ def test_queue_model_orders_every_read_after_its_write(boxes, tiles):
                         assert iv(wq, j)[1] <= s, (q, i, buf, k, "read before write")
                     if nq < 2 * nsteps and (nq, j) != (q, i):
                         assert iv(nq, j)[0] >= e, (q, i, buf, k, "overwritten while read")
+
+
+def test_batch_takes_ideal_gas_boxes_only():
+    cfgs = [_cfg(16, 12), dict(_cfg(20, 16), eos="vdw", eos_a=0.2, eos_b=0.1)]
+    with pytest.raises(rs.RsstError) as e:
+        rs.rsst_batch_plan(cfgs, [16, 16, 16, 16])
+    assert e.value.code == -4  # RSST_E_UNSUPPORTED
