@@ -202,6 +202,9 @@ __host__ __device__ inline Carve carve(int ndim, int ts, int nwx) {
   c.seamP = o;  o += ts * nwx * PL;                       // lane 63 plus-face states
   c.seamPl = o; o += ts * PL;                             // last cell's plus-face state
   c.red = o;    o += 16;
+#ifdef RSST_LDS_PAD
+  if (ndim == 3) o += RSST_LDS_PAD;  // tuning experiments only
+#endif
   c.total = o;
   return c;
 }
