@@ -142,7 +142,11 @@ int rsst_step(rsst_handle h, void* U, double dt_fixed, void* stream);
  * RSST_E_ARG for any other stage number. */
 int rsst_stage(rsst_handle h, void* U, int stage, double dt_fixed, void* stream);
 
-/* nsteps calls of rsst_step. */
+/* nsteps calls of rsst_step, with the same results.  A 1D grid runs as one
+ * workgroup, so for ndim = 1 all nsteps steps are one launch (both stages,
+ * the CFL maximum and the next dt of every step inside it); there, with a
+ * CFL step and t_end > 0, the steps left once t reaches t_end (dt = 0, which
+ * leave U unchanged) are skipped. */
 int rsst_steps(rsst_handle h, void* U, int nsteps, double dt_fixed, void* stream);
 
 /* Synchronises the stream, then returns the time t and the dt the next CFL

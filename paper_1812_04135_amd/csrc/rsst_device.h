@@ -47,7 +47,8 @@ struct Face {
   double vn;
 };
 
-// Reciprocal: hardware seed refined by two Newton steps (about 1 ulp).
+// Reciprocal: hardware seed (relative error about 2^-24 on gfx950) refined
+// by two Newton steps (about 1 ulp).
 __device__ __forceinline__ double rcp(double x) {
   double r = __builtin_amdgcn_rcp(x);
   double e = fma(-x, r, 1.0);
@@ -56,8 +57,9 @@ __device__ __forceinline__ double rcp(double x) {
   return fma(r, e, r);
 }
 
-// Square root of x >= 0: reciprocal-square-root seed and one coupled Newton
-// step on (s, h) = (x y, y/2); sqrt(0) = 0.
+// Square root of x >= 0: reciprocal-square-root seed (relative error about
+// 2^-24 on gfx950) and one coupled Newton step on (s, h) = (x y, y/2), which
+// leaves 1.5 e^2, about 2^-47.6; sqrt(0) = 0.
 __device__ __forceinline__ double sqrt_nr(double x) {
   const double y = __builtin_amdgcn_rsq(fmax(x, 1e-300));
   const double s = x * y, h = 0.5 * y;

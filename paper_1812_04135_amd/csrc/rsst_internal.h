@@ -54,6 +54,10 @@ hipError_t launch_stage(const StageArgs& a, int stage, hipStream_t s);
 // One instantiation per (NDIM, ST) lives in its own object (rsst_stage_inst.hip).
 template <int NDIM, typename ST>
 hipError_t launch_stage_n(const StageArgs& a, int stage, hipStream_t s);
+// nsteps whole steps of a 1D grid (one workgroup) in one launch; a1 and a2
+// are the stage-1 and stage-2 arguments of rsst_stage.
+template <typename ST>
+hipError_t launch_steps1d(const StageArgs& a1, const StageArgs& a2, int nsteps, hipStream_t s);
 hipError_t launch_prime(const StageArgs& a, const void* u, double t0, int set_t, hipStream_t s);
 hipError_t launch_diag(const StageArgs& a, const void* u, double* partial, int npartial,
                        double* out8, hipStream_t s);

@@ -107,4 +107,91 @@ hipError_t launch_stage_n(const StageArgs& a, int stage, hipStream_t s) {
 
 template hipError_t launch_stage_n<RSST_INST_NDIM, RSST_INST_ST>(const StageArgs&, int, hipStream_t);
 
+#if RSST_INST_NDIM == 1
+// nsteps whole steps of a 1D grid in one launch.  A 1D grid is one workgroup
+// (a row of at most 16 waves), so both stages and the CFL maximum of every
+// step run in that workgroup with barriers in between: the stage bodies are
+// those of stage_kernel, the maximum and the next dt are formed as its
+// epilogue forms them, and t and dt stay in registers, so the state, t and dt
+// after each step are bitwise those of the per-stage launches.  Each lane
+// reads back only its own cell between the stages (neighbours come by DPP and
+// LDS), and the workgroup barrier orders those stores and loads.  With a CFL
+// step and an end time, the steps after t reaches t_end (dt = 0, which would
+// leave U unchanged) are skipped.  a1: stage 1 (U -> U1), a2: stage 2.
+template <typename ST, int FORM>
+__global__ void __launch_bounds__(1024) steps1d_kernel(const StageArgs a1, const StageArgs a2, int nsteps) {
+  extern __shared__ double lds[];
+  const Geometry& G = a1.geo;
+  double* red = lds + carve(1, G.ts, G.nwx).red;
+  const bool cfl = !(a1.dt_fixed > 0.0);
+  double t = a1.scal[kTime];
+  double dt = cfl ? a1.scal[kDtCur] : a1.dt_fixed;
+  unsigned bad = 0;
+  for (int q = 0; q < nsteps; ++q) {
+    if (cfl && a1.t_end > 0.0 && !(dt > 0.0)) break;
+    stage_body<1, 1, ST, FORM, 0>(a1, lds, 0, 0, dt, bad);
+    __syncthreads();
+    const double cm = stage_body<1, 2, ST, FORM, 0>(a2, lds, 0, 0, dt, bad);
+    const double wm = wave_max(cm);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = wm;
+    __syncthreads();
+    double m = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, red[w]);
+    t = t + dt;
+    if (cfl) {
+      dt = a1.cfl_h / m;
+      if (a1.t_end > 0.0) dt = fmin(dt, fmax(a1.t_end - t, 0.0));
+    }
+    __syncthreads();
+  }
+  if (bad) atomicOr((unsigned*)(a1.scal + kFlags), bad);
+  if (threadIdx.x == 0) {
+    a1.scal[kTime] = t;
+    a1.scal[kDtCur] = dt;
+  }
+}
+
+template <typename ST, int FORM>
+static hipError_t launch_steps1d_k(const StageArgs& a1, const StageArgs& a2, int nsteps, hipStream_t s) {
+  const Geometry& G = a1.geo;
+  auto kern = steps1d_kernel<ST, FORM>;
+  static int lds_set[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  if ((int)G.lds_bytes > lds_set[dev]) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)G.lds_bytes);
+    if (e != hipSuccess) return e;
+    lds_set[dev] = (int)G.lds_bytes;
+  }
+  hipLaunchKernelGGL(kern, dim3(1), dim3((unsigned)G.threads), G.lds_bytes, s, a1, a2, nsteps);
+  return hipGetLastError();
+}
+
+template <typename ST, int X>
+static hipError_t launch_steps1d_x(const StageArgs& a1, const StageArgs& a2, int n, hipStream_t s) {
+  switch (a1.form) {
+    case kEuler: return launch_steps1d_k<ST, kEuler | X>(a1, a2, n, s);
+    case kPVS: return launch_steps1d_k<ST, kPVS | X>(a1, a2, n, s);
+    case kPMS: return launch_steps1d_k<ST, kPMS | X>(a1, a2, n, s);
+    case kDVS: return launch_steps1d_k<ST, kDVS | X>(a1, a2, n, s);
+    case kDMS: return launch_steps1d_k<ST, kDMS | X>(a1, a2, n, s);
+    default: return launch_steps1d_k<ST, kPD | X>(a1, a2, n, s);
+  }
+}
+
+template <typename ST>
+hipError_t launch_steps1d(const StageArgs& a1, const StageArgs& a2, int nsteps, hipStream_t s) {
+  if (a1.geo.ndim != 1 || a1.geo.ntile_s * a1.geo.nchunk != 1) return hipErrorInvalidValue;
+  if constexpr (sizeof(ST) == 8) {
+    if (a1.eos) return launch_steps1d_x<ST, kExtVdw>(a1, a2, nsteps, s);
+  }
+  if (a1.eos) return hipErrorInvalidValue;
+  return a1.inv_cmax2 > 0.0 ? launch_steps1d_x<ST, kExtCmax>(a1, a2, nsteps, s)
+                            : launch_steps1d_x<ST, 0>(a1, a2, nsteps, s);
+}
+
+template hipError_t launch_steps1d<RSST_INST_ST>(const StageArgs&, const StageArgs&, int, hipStream_t);
+#endif
+
 }  // namespace rsstk
