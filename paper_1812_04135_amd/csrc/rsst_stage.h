@@ -49,36 +49,45 @@ __device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, int voff, i
   }
 }
 
+// Cache policy of the stage outputs and of the pointwise step-start reads
+// (no reuse within a stage): 0 default, 2 non-temporal (tuning).
+#ifndef RSST_ST_AUX
+#define RSST_ST_AUX 0
+#endif
+#ifndef RSST_UN_AUX
+#define RSST_UN_AUX 0
+#endif
+
 template <typename ST>
 __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, int voff, int soff, ST x) {
   if constexpr (sizeof(ST) == 8) {
     u32x2_t v;
     v.x = (unsigned)__double2loint(x);
     v.y = (unsigned)__double2hiint(x);
-    __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, RSST_ST_AUX);
   } else {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, voff, soff, RSST_ST_AUX);
   }
 }
 
 // The stored values of a cell, as loaded (no conversion): the loads can be
 // issued early and their results used a phase later, with no wait in between.
-template <typename ST>
+template <typename ST, int AUX = 0>
 __device__ __forceinline__ ST buf_load_raw(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
   if constexpr (sizeof(ST) == 8) {
-    const u32x2_t v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    const u32x2_t v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, AUX);
     return __hiloint2double((int)v.y, (int)v.x);
   } else {
-    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, AUX));
   }
 }
 
-template <int NDIM, typename ST>
+template <int NDIM, typename ST, int AUX = 0>
 __device__ __forceinline__ void load_cell_raw(const StageArgs& A, __amdgpu_buffer_rsrc_t r, int soff, int voff,
                                               ST (&raw)[NDIM + 2]) {
   const int vstride = (int)(A.ncell * (long long)sizeof(ST));
 #pragma unroll
-  for (int v = 0; v < NDIM + 2; ++v) raw[v] = buf_load_raw<ST>(r, voff, soff + v * vstride);
+  for (int v = 0; v < NDIM + 2; ++v) raw[v] = buf_load_raw<ST, AUX>(r, voff, soff + v * vstride);
 }
 
 // FP64 cell state from its stored values: widening and background (FP32
@@ -387,7 +396,7 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
       q2neg = n ? NDIM : -1;
       load_cell_raw<NDIM, ST>(A, uin, q2k * plane, col, q2r);
     }
-    if constexpr (STAGE == 2) load_cell_raw<NDIM, ST>(A, unp, koff, col, unr);
+    if constexpr (STAGE == 2) load_cell_raw<NDIM, ST, RSST_UN_AUX>(A, unp, koff, col, unr);
     if constexpr (F32) {
       if (bg_on_m) {
         load_bg<NV>(bgr, A.nbg, k, bgA);

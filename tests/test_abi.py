@@ -89,6 +89,17 @@ def test_unsupported_shape_reported():
     c = R.make_config(cfg)
     h = ctypes.c_void_p()
     assert R.lib().rsst_init(ctypes.byref(c), None, ctypes.byref(h)) == -4
+    # rows wider than one workgroup, and fields past 2 GiB (32-bit byte
+    # offsets), are reported on the host; the largest supported ones pass
+    # validation up to the device allocation (not attempted here)
+    for n, ok in (([1025], False), ([1025, 8], False), ([256, 256, 819], True), ([256, 256, 820], False)):
+        cfg = W.base_cfg(len(n), n)
+        c = R.make_config(cfg)
+        code = R.lib().rsst_init(ctypes.byref(c), None, ctypes.byref(h))
+        assert (code != -4) if ok else (code == -4), (n, code)
+        if h.value:
+            R.lib().rsst_destroy(h)
+            h = ctypes.c_void_p()
 
 
 def test_adjoint_flags_validated_on_host():

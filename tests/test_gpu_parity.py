@@ -94,6 +94,7 @@ CASES = [
     (2, [130, 12], ["reflect", "reflect"], [0.1, -0.4], "dms"),
     (2, [20, 33], ["periodic", "reflect"], [0.0, -1.0], "pd"),
     (2, [200, 8], ["periodic", "periodic"], None, "euler"),
+    (2, [1024, 6], ["periodic", "reflect"], [0.0, -0.3], "pvs"),  # widest 2D row (16 waves)
     (3, [37, 13, 11], ["periodic"] * 3, None, "pvs"),
     (3, [20, 9, 10], ["periodic", "periodic", "reflect"], [0.0, 0.0, -1.0], "pvs"),
     (3, [130, 9, 6], ["reflect", "reflect", "periodic"], [0.3, -0.2, 0.0], "pms"),
