@@ -117,8 +117,9 @@ typedef struct rsst_solver* rsst_handle;
 
 /* Validates cfg on the host before touching the device (RSST_E_ARG on any
  * invalid field), then allocates the workspace (stage buffer, reduction
- * scalars) on the current device.  t starts at 0.  No allocation happens
- * after this call. */
+ * scalars) on the current device and zeroes the scalars on `stream`,
+ * synchronising it before returning (so later calls may use any stream).
+ * t starts at 0.  No allocation happens after this call. */
 int rsst_init(const rsst_config* cfg, void* stream, rsst_handle* out);
 
 /* Sets t = t0 and computes the CFL time step of state U on the device.

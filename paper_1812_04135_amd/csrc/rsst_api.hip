@@ -102,7 +102,7 @@ const char* rsst_strerror(int s) {
   }
 }
 
-const char* rsst_version(void) { return "rsst-gfx950 stage-v7"; }
+const char* rsst_version(void) { return "rsst-gfx950 stage-v8"; }
 
 int rsst_init(const rsst_config* cfg, void* stream, rsst_handle* out) {
   if (!out) return RSST_E_ARG;
@@ -159,7 +159,8 @@ int rsst_init(const rsst_config* cfg, void* stream, rsst_handle* out) {
   h->npart = rsstk::diag_partials(h->ncell);
   const size_t ubytes = (size_t)h->nv * h->ncell * h->elem;
   if (hipMalloc(&h->u1, ubytes) != hipSuccess) { delete h; return RSST_E_NOMEM; }
-  if (hipMalloc((void**)&h->scal, rsstk::kNumScalars * sizeof(double)) != hipSuccess ||
+  const size_t nscal = rsstk::kNumScalars;
+  if (hipMalloc((void**)&h->scal, nscal * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&h->part, (size_t)h->npart * 8 * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&h->diag_out, 8 * sizeof(double)) != hipSuccess) {
     (void)hipFree(h->u1); (void)hipFree(h->scal); (void)hipFree(h->part); (void)hipFree(h->diag_out);
@@ -175,7 +176,9 @@ int rsst_init(const rsst_config* cfg, void* stream, rsst_handle* out) {
       return RSST_E_NOMEM;
     }
   }
-  if (hipMemsetAsync(h->scal, 0, rsstk::kNumScalars * sizeof(double), s) != hipSuccess) {
+  // zeroed before any launch on any stream
+  if (hipMemsetAsync(h->scal, 0, nscal * sizeof(double), s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
     rsst_destroy(h);
     return RSST_E_DEVICE;
   }
