@@ -28,7 +28,8 @@
 //             cell (Mb), the alpha part of xi_bar;
 //   A4 cell   U_bar += Pb + Mb, reverse of the MC half slope h = (Pb-Mb):
 //             slope cotangents (lb, rb), stored over Pb and Mb;
-//   A5 cell   U_bar gathers -lb of the cell above and +rb of the cell below.
+//   A5 cell   U_bar gathers -lb of the cell above and +rb of the cell below,
+//             and forms mu (first VJP) or the new lam (second VJP) from it.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -60,6 +61,12 @@ struct AdjArgs {
   double* Mb;        // [ndim][nv][ncell]
   double* xpart;     // [2][nblock] partial sums of xi_bar
   int nblock;
+  // what the last pass does with its result r = J_R^T W (per element):
+  // 0: out = r; 1: mu = (lam + dt r)/2; 2: lam = lam/2 + mu + dt r
+  int post;
+  double* lam;
+  double* mu;
+  double dt;
 };
 
 __device__ __forceinline__ void cell_coords(const AdjArgs& A, long long c, int x[3]) {
@@ -583,22 +590,22 @@ __global__ void __launch_bounds__(kAdjThreads) adj_gather_kernel(AdjArgs A) {
   a5_axis<NDIM, 0>(A, c, x, ub);
   if constexpr (NDIM >= 2) a5_axis<NDIM, 1>(A, c, x, ub);
   if constexpr (NDIM >= 3) a5_axis<NDIM, 2>(A, c, x, ub);
+  if (A.post == 1) {
 #pragma unroll
-  for (int v = 0; v < NV; ++v) A.out[v * A.ncell + c] = ub[v];
-}
-
-// mu = (lam + dt a) / 2
-__global__ void __launch_bounds__(kAdjThreads) adj_mu_kernel(const double* lam, const double* a, double* mu,
-                                                            double dt, long long n) {
-  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < n) mu[q] = 0.5 * (lam[q] + dt * a[q]);
-}
-
-// lam = lam / 2 + mu + dt b
-__global__ void __launch_bounds__(kAdjThreads) adj_lam_kernel(double* lam, const double* mu, const double* b,
-                                                             double dt, long long n) {
-  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < n) lam[q] = 0.5 * lam[q] + mu[q] + dt * b[q];
+    for (int v = 0; v < NV; ++v) {
+      const long long q = v * A.ncell + c;
+      A.mu[q] = 0.5 * (A.lam[q] + A.dt * ub[v]);
+    }
+  } else if (A.post == 2) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const long long q = v * A.ncell + c;
+      A.lam[q] = 0.5 * A.lam[q] + A.mu[q] + A.dt * ub[v];
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) A.out[v * A.ncell + c] = ub[v];
+  }
 }
 
 // dJdxi += dt/2 (sum of the U1 partials) + dt (sum of the U partials), in a
@@ -695,26 +702,28 @@ hipError_t launch_adjoint_step(const AdjointPlan& p, const double* U, const doub
   double* part1 = mu + nf;
   double* part2 = part1 + 2 * nblock;
   A.nblock = nblock;
-  const dim3 eg((unsigned)((nf + kAdjThreads - 1) / kAdjThreads)), eb(kAdjThreads);
-  auto vjp = [&](const double* V, const double* Wc, double* out, double* part) {
+  const dim3 eb(kAdjThreads);
+  A.lam = lam;
+  A.mu = mu;
+  A.dt = dt;
+  auto vjp = [&](const double* V, const double* Wc, double* out, double* part, int post) {
     A.V = V;
     A.W = Wc;
     A.out = out;
     A.xpart = part;
+    A.post = post;
     switch (ndim) {
       case 1: return vjp_launch<1>(A, p.form, s);
       case 2: return vjp_launch<2>(A, p.form, s);
       default: return vjp_launch<3>(A, p.form, s);
     }
   };
-  // (a, s1) = VJP(U1, lam); mu = (lam + dt a)/2
-  hipError_t e = vjp(U1, lam, ab, part1);
+  // (a, s1) = VJP(U1, lam) with mu = (lam + dt a)/2 formed by its last pass
+  hipError_t e = vjp(U1, lam, ab, part1, 1);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(adj_mu_kernel, eg, eb, 0, s, lam, ab, mu, dt, nf);
-  // (b, s2) = VJP(U, mu); lam = lam/2 + mu + dt b
-  e = vjp(U, mu, ab, part2);
+  // (b, s2) = VJP(U, mu) with lam = lam/2 + mu + dt b formed by its last pass
+  e = vjp(U, mu, ab, part2, 2);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(adj_lam_kernel, eg, eb, 0, s, lam, mu, ab, dt, nf);
   // each VJP left partials of the f part then the alpha part: 2 nblock each
   hipLaunchKernelGGL(adj_xi_kernel, dim3(1), eb, 0, s, part1, part2, 2 * nblock, dt, dJdxi);
   return hipGetLastError();
