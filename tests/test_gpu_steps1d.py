@@ -127,3 +127,24 @@ def test_nonphysical_state_flagged_in_one_launch():
         s.poll()
     assert e.value.flags & 1
     s.close()
+
+
+@pytest.mark.parametrize("ndim,n", [(1, [64]), (2, [40, 12]), (3, [37, 9, 8])])
+def test_zero_steps_and_steps_past_end_time_change_nothing(ndim, n):
+    """nsteps = 0 leaves U, t and dt as they are; after t reaches t_end the
+    remaining steps are no-ops (dt = 0), in every dimension."""
+    cfg, U0 = W.random_state(ndim, n, seed_k=750 + ndim, xi=3.0)
+    U = torch.from_numpy(U0.copy()).cuda()
+    s = R.Solver(cfg, t_end=0.01)
+    s.steps(U, 0)
+    torch.cuda.synchronize()
+    assert np.array_equal(U.cpu().numpy(), U0) and s.time()[0] == 0.0
+    s.steps(U, 100000 if ndim == 1 else 400)
+    t, dt = s.time()
+    assert t == pytest.approx(0.01, rel=1e-14) and dt == 0.0
+    Ue = U.cpu().numpy()
+    s.steps(U, 5)
+    s.step(U)
+    torch.cuda.synchronize()
+    assert np.array_equal(U.cpu().numpy(), Ue) and s.time() == (t, 0.0)
+    s.close()
