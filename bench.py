@@ -454,8 +454,10 @@ def main():
     ms2 = timed(s2, U2, 200)
     s2.close()
     n2 = U2_0[0].size
+    nv2 = U2_0.shape[0]
     sec["bubble2d_512_fp64"] = {"ms_per_step": round(ms2, 5),
-                                "Gcell_updates_s": round(n2 / (ms2 * 1e-3) / 1e9, 4)}
+                                "Gcell_updates_s": round(n2 / (ms2 * 1e-3) / 1e9, 4),
+                                "effective_GBs": round(5 * nv2 * 8 * n2 / (ms2 * 1e-3) / 1e9, 1)}
     # the same bubble as an FP32 perturbation about the uniform ambient state
     bg2 = torch.from_numpy(meta2["bg"]).to(dev)
     U2p0 = (U2_0 - meta2["bg"][:, :, None]).astype(np.float32)
@@ -465,6 +467,7 @@ def main():
     s2p.close()
     sec["bubble2d_512_fp32_pert"] = {"ms_per_step": round(ms2p, 5),
                                      "Gcell_updates_s": round(n2 / (ms2p * 1e-3) / 1e9, 4),
+                                     "effective_GBs": round(5 * nv2 * 4 * n2 / (ms2p * 1e-3) / 1e9, 1),
                                      "speedup_vs_fp64": round(ms2 / ms2p, 3)}
     # FP64 diagnostics (sums, kinetic energy, maxima) of the 256^3 state
     td = time.perf_counter()
