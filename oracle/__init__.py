@@ -21,7 +21,7 @@ _SRC = os.path.join(_HERE, "rsst_oracle.cpp")
 _LIB = os.path.join(_HERE, "librsst_oracle.so")
 
 FORMS = {"euler": 0, "pvs": 1, "pms": 2, "dvs": 3, "dms": 4, "pd": 5}
-BCS = {"periodic": 0, "reflect": 1}
+BCS = {"periodic": 0, "reflect": 1, "hydro": 2}
 EOS = {"ideal": 0, "vdw": 1}
 
 

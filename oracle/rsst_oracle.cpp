@@ -65,7 +65,8 @@ typedef struct {
   double cfl;      // Courant number
   int dt_rule;     // 0: h = 1/sum(1/dx), 1: h = min(dx)
   double g[3];     // external force per unit mass
-  int bc_lo[3];    // 0 periodic, 1 reflecting (closed free-slip)
+  int bc_lo[3];    // 0 periodic, 1 reflecting (closed free-slip), 2 reflecting
+                   // with the ghost pressure extrapolated hydrostatically
   int bc_hi[3];
   int form;        // 0 Euler, 1 PVS, 2 PMS, 3 DVS, 4 DMS, 5 PD
   double cmax;     // > 0: xi from the upper limit of the sound speed (eq. cx)
@@ -80,7 +81,7 @@ typedef struct {
 }  // extern "C"
 
 enum { F_EULER = 0, F_PVS = 1, F_PMS = 2, F_DVS = 3, F_DMS = 4, F_PD = 5 };
-enum { BC_PERIODIC = 0, BC_REFLECT = 1 };
+enum { BC_PERIODIC = 0, BC_REFLECT = 1, BC_HYDRO = 2 };
 
 // ---------------------------------------------------------------------------
 // Scalar types
@@ -372,6 +373,7 @@ struct Grid {
   int64_t ncell;
 };
 
+
 static Gas gas_of(const ora_config* c) {
   Gas g = c->eos == 1 ? Gas{c->gamma, 1, c->eos_a, c->eos_b, 0.0} : ideal_gas(c->gamma);
   g.probe = c->p_probe;
@@ -394,21 +396,42 @@ static inline int64_t cell_index(const Grid& G, int i, int j, int k) {
 // Value of variable v at cell index idx[] where at most one axis may lie in
 // the two-layer ghost zone.  Periodic sides wrap; reflecting sides mirror
 // (ghost -1-k takes cell k) and negate the momentum normal to that side.
+// A hydrostatic wall (reading of the closed wall's hydrostatic variant) also
+// gives the ghost the pressure of cell k carried to the ghost centre along
+// the external force: P_g = P_k + rho_k g_d (x_g - x_k), x_g - x_k = -(2k+1) dx
+// below the domain and +(2k+1) dx above it; rho and |V| are the mirrored
+// ones, so E changes by (P_g - P_k)(de/dP)_rho.
 template <class S>
 static S ghosted(const Grid& G, const ora_config* c, const S* U, int v, const int idx[3]) {
   int id[3] = {idx[0], idx[1], idx[2]};
   double sign = 1.0;
+  double lever = 0.0;  // (x_g - x_k) g_d for a hydrostatic ghost
   for (int d = 0; d < G.ndim; ++d) {
     const int n = G.n[d];
     if (id[d] < 0) {
       if (c->bc_lo[d] == BC_PERIODIC) id[d] += n;
-      else { id[d] = -1 - id[d]; if (v == 1 + d) sign = -sign; }
+      else {
+        const int k = -1 - id[d];
+        if (c->bc_lo[d] == BC_HYDRO) lever = -(2.0 * k + 1.0) * c->dx[d] * c->g[d];
+        id[d] = k;
+        if (v == 1 + d) sign = -sign;
+      }
     } else if (id[d] >= n) {
       if (c->bc_hi[d] == BC_PERIODIC) id[d] -= n;
-      else { id[d] = 2 * n - 1 - id[d]; if (v == 1 + d) sign = -sign; }
+      else {
+        const int k = id[d] - n;
+        if (c->bc_hi[d] == BC_HYDRO) lever = (2.0 * k + 1.0) * c->dx[d] * c->g[d];
+        id[d] = n - 1 - k;
+        if (v == 1 + d) sign = -sign;
+      }
     }
   }
-  S x = U[(int64_t)v * G.ncell + cell_index(G, id[0], id[1], id[2])];
+  const int64_t ci = cell_index(G, id[0], id[1], id[2]);
+  S x = U[(int64_t)v * G.ncell + ci];
+  if (v == G.nv - 1 && lever != 0.0) {
+    const S rho = U[ci];
+    x = x + rho * lever * eos_dedP(gas_of(c), rho);
+  }
   return (sign < 0) ? -x : x;
 }
 

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "librsst.so")
 RSST_OK = 0
 RSST_E_NONPHYSICAL = -5
 FORMS = {"euler": 0, "pvs": 1, "pms": 2, "dvs": 3, "dms": 4, "pd": 5}
-BCS = {"periodic": 0, "reflect": 1}
+BCS = {"periodic": 0, "reflect": 1, "hydro": 2}
 PRECS = {"fp64": 0, "fp32_pert": 1}
 EOS = {"ideal": 0, "vdw": 1}
 RSST_WITH_ADJOINT = 1

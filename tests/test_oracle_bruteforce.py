@@ -1,11 +1,12 @@
 """A second, brute-force transcription of the scheme on tiny grids (pure
 Python, scalar loops), against the C++ oracle: 8 cells in 1D, 6 x 5 in 2D,
-4 x 4 x 4 in 3D, every form, periodic and mirror walls, gravity, the C_max law
-and the van der Waals gas, two SSP-RK2 steps at a fixed dt.
+4 x 4 x 4 in 3D, every form, periodic, mirror and hydrostatic walls, gravity,
+the C_max law and the van der Waals gas, two SSP-RK2 steps at a fixed dt.
 
 It is organised differently from the oracle on purpose: the grid is copied
 into an array padded with two explicit ghost layers per side (filled by
-wrapping or mirroring, Sec. 4.2 and 4.4), every face flux is computed once into
+wrapping or mirroring, Sec. 4.2 and 4.4; a hydrostatic wall's ghost takes its
+pressure from the equation of state at the carried pressure), every face flux is computed once into
 a face array, and the divergence is assembled from those arrays.  What both
 follow is the paper's step: MUSCL with MC on the conservative variables,
 LLF with c_tot = |V| + a/xi (Sec. 4.1), the divergence (eq. pvs_dt0), Delta P
@@ -70,28 +71,43 @@ def mc(l, r):
     return s * min(abs(l + r) / 2.0, 2.0 * abs(l), 2.0 * abs(r))
 
 
-def padded(U, cfg):
-    """Copy of U with two ghost layers per side of each used axis."""
+def padded(U, cfg, gas=None):
+    """Copy of U with two ghost layers per side of each used axis.  A
+    'hydro' wall's ghost carries the mirrored cell's pressure to the ghost
+    centre with the hydrostatic gradient rho g_d (rho and |V| mirrored)."""
     nd = cfg["ndim"]
     n = cfg["n"][:nd]
     nv = nd + 2
     shape = [n[d] + 4 for d in range(nd)]
     Pd = np.zeros([nv] + shape[::-1])
-    for v in range(nv):
-        field = U[v].reshape(n[::-1])
-        for gidx in product(*[range(-2, n[d] + 2) for d in range(nd)]):
-            src = list(gidx)
-            sign = 1.0
-            for d in range(nd):
-                if src[d] < 0 or src[d] >= n[d]:
-                    periodic = cfg["bc_lo"][d] == "periodic"
-                    if periodic:
-                        src[d] %= n[d]
-                    else:
-                        src[d] = -1 - src[d] if src[d] < 0 else 2 * n[d] - 1 - src[d]
-                        if v == 1 + d:
-                            sign = -sign
-            Pd[(v,) + tuple(g + 2 for g in gidx[::-1])] = sign * field[tuple(src[::-1])]
+    fields = [U[v].reshape(n[::-1]) for v in range(nv)]
+    for gidx in product(*[range(-2, n[d] + 2) for d in range(nd)]):
+        src = list(gidx)
+        neg = -1
+        shift = 0.0  # x_ghost - x_source along the wall's axis
+        wall = None
+        for d in range(nd):
+            if src[d] < 0 or src[d] >= n[d]:
+                side = "bc_lo" if src[d] < 0 else "bc_hi"
+                if cfg[side][d] == "periodic":
+                    src[d] %= n[d]
+                else:
+                    mirror = -1 - src[d] if src[d] < 0 else 2 * n[d] - 1 - src[d]
+                    shift = (gidx[d] - mirror) * cfg["dx"][d]
+                    src[d] = mirror
+                    neg = d
+                    wall = cfg[side][d], d
+        vals = [fields[v][tuple(src[::-1])] for v in range(nv)]
+        if neg >= 0:
+            vals[1 + neg] = -vals[1 + neg]
+        if wall is not None and wall[0] == "hydro":
+            rho = vals[0]
+            v2 = sum((vals[1 + e] / rho) ** 2 for e in range(nd))
+            P = P_of(rho, vals[nv - 1] - 0.5 * rho * v2, gas)
+            Pg = P + rho * cfg["g"][wall[1]] * shift
+            vals[nv - 1] = e_of(rho, Pg, gas) + 0.5 * rho * v2
+        for v in range(nv):
+            Pd[(v,) + tuple(g + 2 for g in gidx[::-1])] = vals[v]
     return Pd
 
 
@@ -101,7 +117,7 @@ def rate(U, cfg, gas=None):
     nv = nd + 2
     xi, cmax = cfg["xi"], cfg.get("cmax", 0.0)
     form = cfg["form"]
-    Pd = padded(U, cfg)
+    Pd = padded(U, cfg, gas)
 
     def at(v, idx):  # idx: cell index per axis (may be -2..n+1)
         return Pd[(v,) + tuple(i + 2 for i in idx[::-1])]
@@ -199,6 +215,10 @@ CASES = [
     (2, [6, 5], ["periodic", "periodic"], [0.0, 0.0], "euler"),
     (3, [4, 4, 4], ["periodic", "periodic", "reflect"], [0.0, 0.0, -1.0], "pvs"),
     (3, [4, 4, 4], ["reflect", "periodic", "periodic"], [0.2, 0.0, 0.0], "pd"),
+    (1, [8], ["hydro"], [-0.7], "pvs"),
+    (2, [6, 5], ["periodic", "hydro"], [0.0, -0.8], "pms"),
+    (2, [6, 5], ["hydro", "hydro"], [0.3, -0.5], "dvs"),
+    (3, [4, 4, 4], ["periodic", "hydro", "hydro"], [0.0, 0.4, -1.0], "pd"),
 ]
 
 
