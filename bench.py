@@ -174,11 +174,17 @@ def run_to(s, U, t_end):
 
 def bench_rt(R, W, np, torch, stream, n=256):
     """Sec. 4.4 Rayleigh-Taylor at n^2 to t = 2.5: xi = 1 against the RSST at
-    xi = 6.3 (PVS and PMS): steps, GPU time, max |V_y| and the L1 distance of
-    the density field from the xi = 1 run."""
+    xi = 6.3 (PVS and PMS), at C_max = 10 (PVS, xi from each state's sound
+    speed), and at xi = 6.3 with hydrostatic walls: steps, GPU time, max |V_y|
+    and the L1 distance of the density field from the xi = 1 run."""
     out, ref = {}, None
-    for form, xi in (("pvs", 1.0), ("pvs", 6.3), ("pms", 6.3)):
+    for form, xi, extra in (("pvs", 1.0, ""), ("pvs", 6.3, ""), ("pms", 6.3, ""), ("pvs", 1.0, "cmax10"),
+                            ("pvs", 6.3, "hydro")):
         cfg, U0, meta = W.rt2d(n, form=form, xi=xi)
+        if extra == "cmax10":
+            cfg["cmax"] = 10.0
+        elif extra == "hydro":
+            cfg = dict(cfg, bc_lo=["periodic", "hydro"], bc_hi=["periodic", "hydro"])
         U = torch.from_numpy(U0).cuda()
         s = R.Solver(cfg, t_end=meta["t_end"])
         torch.cuda.synchronize()
@@ -188,7 +194,7 @@ def bench_rt(R, W, np, torch, stream, n=256):
         wall = time.perf_counter() - w0
         s.close()
         Un = U.cpu().numpy()
-        key = f"{form}_xi{xi:g}"
+        key = f"{form}_cmax10" if extra == "cmax10" else f"{form}_xi{xi:g}" + (f"_{extra}" if extra else "")
         out[key] = {"steps": steps, "wall_s": round(wall, 3), "max_abs_Vy": float(np.abs(Un[2] / Un[0]).max())}
         if ref is None:
             ref = Un[0]

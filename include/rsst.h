@@ -54,7 +54,16 @@ enum rsst_status {
 
 enum rsst_form { RSST_EULER = 0, RSST_PVS = 1, RSST_PMS = 2, RSST_DVS = 3,
                  RSST_DMS = 4, RSST_PD = 5 };
-enum rsst_bc { RSST_PERIODIC = 0, RSST_REFLECT = 1 };
+/* Boundary of one side of an axis (Sec. 4.2 periodic, Sec. 4.4 closed
+ * free-slip walls).  RSST_REFLECT: mirror ghosts (two layers), the momentum
+ * normal to the wall negated; no mass or energy crosses the wall.
+ * RSST_REFLECT_HYDRO: the same ghosts, but each ghost's pressure is its
+ * mirrored cell's carried to the ghost centre along the external force,
+ * P_g = P_k + rho_k g_d (x_g - x_k), which balances gravity at the wall face
+ * (no mass crosses the wall; energy does, at O(dx)).  FP64 only, not with
+ * the adjoint or the batch, and on axis 0 only with g[0] = 0 (where it is
+ * RSST_REFLECT); otherwise RSST_E_UNSUPPORTED. */
+enum rsst_bc { RSST_PERIODIC = 0, RSST_REFLECT = 1, RSST_REFLECT_HYDRO = 2 };
 enum rsst_prec { RSST_FP64 = 0, RSST_FP32_PERT = 1 };
 
 typedef struct rsst_config {

@@ -43,8 +43,8 @@ static int validate(const rsst_config* c) {
     if (d < c->ndim) {
       if (c->n[d] < 4) return RSST_E_ARG;
       if (!(c->dx[d] > 0.0) || !std::isfinite(c->dx[d])) return RSST_E_ARG;
-      if (c->bc_lo[d] != RSST_PERIODIC && c->bc_lo[d] != RSST_REFLECT) return RSST_E_ARG;
-      if (c->bc_hi[d] != RSST_PERIODIC && c->bc_hi[d] != RSST_REFLECT) return RSST_E_ARG;
+      if (c->bc_lo[d] < RSST_PERIODIC || c->bc_lo[d] > RSST_REFLECT_HYDRO) return RSST_E_ARG;
+      if (c->bc_hi[d] < RSST_PERIODIC || c->bc_hi[d] > RSST_REFLECT_HYDRO) return RSST_E_ARG;
       if ((c->bc_lo[d] == RSST_PERIODIC) != (c->bc_hi[d] == RSST_PERIODIC)) return RSST_E_ARG;
       if (!std::isfinite(c->g[d])) return RSST_E_ARG;
     } else if (c->n[d] != 1) {
@@ -67,6 +67,16 @@ static int validate(const rsst_config* c) {
   if ((c->flags & RSST_WITH_ADJOINT) && c->cmax > 0.0) return RSST_E_UNSUPPORTED;
   if ((c->flags & RSST_WITH_ADJOINT) && c->prec != RSST_FP64) return RSST_E_UNSUPPORTED;
   if (c->eos != RSST_EOS_IDEAL && c->eos != RSST_EOS_VDW) return RSST_E_ARG;
+  {
+    // hydrostatic walls: FP64, no adjoint, and along x only where they equal
+    // the mirror wall (no force along x: x walls mirror face states in-row)
+    bool hydro = false;
+    for (int d = 0; d < c->ndim; ++d)
+      hydro = hydro || c->bc_lo[d] == RSST_REFLECT_HYDRO || c->bc_hi[d] == RSST_REFLECT_HYDRO;
+    if (hydro && (c->prec != RSST_FP64 || (c->flags & RSST_WITH_ADJOINT))) return RSST_E_UNSUPPORTED;
+    if ((c->bc_lo[0] == RSST_REFLECT_HYDRO || c->bc_hi[0] == RSST_REFLECT_HYDRO) && c->g[0] != 0.0)
+      return RSST_E_UNSUPPORTED;
+  }
   if (c->eos == RSST_EOS_VDW) {
     if (!(c->eos_a >= 0.0) || !std::isfinite(c->eos_a)) return RSST_E_ARG;
     if (!(c->eos_b >= 0.0) || !std::isfinite(c->eos_b)) return RSST_E_ARG;
@@ -102,7 +112,7 @@ const char* rsst_strerror(int s) {
   }
 }
 
-const char* rsst_version(void) { return "rsst-gfx950 stage-v8"; }
+const char* rsst_version(void) { return "rsst-gfx950 stage-v9"; }
 
 int rsst_init(const rsst_config* cfg, void* stream, rsst_handle* out) {
   if (!out) return RSST_E_ARG;
@@ -127,6 +137,9 @@ int rsst_init(const rsst_config* cfg, void* stream, rsst_handle* out) {
     a.bc_lo[d] = cfg->bc_lo[d];
     a.bc_hi[d] = cfg->bc_hi[d];
     a.inv_dx[d] = d < cfg->ndim ? 1.0 / cfg->dx[d] : 0.0;
+    a.dx[d] = d < cfg->ndim ? cfg->dx[d] : 0.0;
+    if (d >= 1 && d < cfg->ndim && (cfg->bc_lo[d] == RSST_REFLECT_HYDRO || cfg->bc_hi[d] == RSST_REFLECT_HYDRO))
+      a.hydro = 1;
     a.g[d] = d < cfg->ndim ? cfg->g[d] : 0.0;
   }
   a.gamma = cfg->gamma;

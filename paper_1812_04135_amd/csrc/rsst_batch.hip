@@ -254,7 +254,8 @@ static int batch_validate(const rsst_config* c, int nbox, const int64_t* off) {
     if (k.n[0] > 256) return RSST_E_UNSUPPORTED;
     if (!(k.dx[0] > 0) || !(k.dx[1] > 0)) return RSST_E_ARG;
     for (int d = 0; d < 2; ++d) {
-      if (k.bc_lo[d] != RSST_PERIODIC && k.bc_lo[d] != RSST_REFLECT) return RSST_E_ARG;
+      if (k.bc_lo[d] < RSST_PERIODIC || k.bc_lo[d] > RSST_REFLECT_HYDRO) return RSST_E_ARG;
+      if (k.bc_hi[d] < RSST_PERIODIC || k.bc_hi[d] > RSST_REFLECT_HYDRO) return RSST_E_ARG;
       if ((k.bc_lo[d] == RSST_PERIODIC) != (k.bc_hi[d] == RSST_PERIODIC)) return RSST_E_ARG;
     }
     if (!(k.gamma > 1.0) || !(k.xi >= 1.0) || !(k.cfl > 0.0 && k.cfl <= 1.0)) return RSST_E_ARG;
@@ -262,6 +263,8 @@ static int batch_validate(const rsst_config* c, int nbox, const int64_t* off) {
     if (k.form < RSST_EULER || k.form > RSST_PD) return RSST_E_ARG;
     if (k.prec == RSST_FP32_PERT && (!k.bg || (k.bg_axis != -1 && k.bg_axis != 1))) return RSST_E_ARG;
     if (k.t_end != 0.0 || k.cmax != 0.0 || k.flags != 0 || k.eos != RSST_EOS_IDEAL) return RSST_E_UNSUPPORTED;
+    for (int d = 0; d < 2; ++d)
+      if (k.bc_lo[d] == RSST_REFLECT_HYDRO || k.bc_hi[d] == RSST_REFLECT_HYDRO) return RSST_E_UNSUPPORTED;
     if (off[b] < 0) return RSST_E_ARG;
     const long long bytes = 4ll * k.n[0] * k.n[1] * (k.prec == RSST_FP32_PERT ? 4 : 8);
     if (bytes >= (1ll << 31)) return RSST_E_UNSUPPORTED;

@@ -33,9 +33,9 @@ struct Consts {
 };
 
 // Extension bits of a kernel's template argument, above the form (0..5):
-// xi from the sound speed (eq. cx), and the van der Waals equation of state
-// in place of the ideal gas.
-enum Ext { kExtCmax = 8, kExtVdw = 16 };
+// xi from the sound speed (eq. cx), the van der Waals equation of state in
+// place of the ideal gas, and hydrostatic walls on the y or march axis.
+enum Ext { kExtCmax = 8, kExtVdw = 16, kExtHydro = 32 };
 
 // A reconstructed face state: conservative values plus the primitive
 // quantities the LLF flux needs.  `vn` is the velocity normal to the face.

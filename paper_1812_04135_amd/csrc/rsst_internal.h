@@ -28,9 +28,11 @@ struct StageArgs {
   long long ncell;
   int bc_lo[3], bc_hi[3];  // physical axes
   double inv_dx[3];
+  double dx[3];      // cell widths (hydrostatic wall ghosts)
   double gamma, gm1, inv_gm1, inv_xi, f;
   double inv_cmax2;  // > 0: xi = [1 + (a/C_max)^4]^(1/4) per state (eq. cx)
   int eos;           // 0 ideal gas, 1 van der Waals (a, b below)
+  int hydro;         // a hydrostatic wall on the y or march axis (2D/3D)
   double vdw_a, vdw_b;
   double g[3];
   int form;

@@ -29,6 +29,17 @@ __device__ __forceinline__ int map_index(int q, int n, int refl_lo, int refl_hi,
   return q;
 }
 
+// Hydrostatic closed wall (bc 2): the ghost at raw index q (outside [0, n))
+// mirrors cell k and carries its pressure to the ghost centre along the
+// external force, P_g = P_k + rho_k g (x_g - x_k); returns (x_g - x_k) g,
+// 0 for any other cell or wall.  x_g - x_k = (2q + 1) dx below the domain
+// (q = -1 - k) and (2(q - n) + 1) dx above it.
+__device__ __forceinline__ double hydro_lever(int q, int n, int bc_lo, int bc_hi, double dx, double g) {
+  if (q < 0) return bc_lo == 2 ? (2.0 * q + 1.0) * dx * g : 0.0;
+  if (q >= n) return bc_hi == 2 ? (2.0 * (q - n) + 1.0) * dx * g : 0.0;
+  return 0.0;
+}
+
 // Raw buffer access to a field: one resource per field (bounds-checked by
 // the hardware against the field's byte size), a workgroup-uniform byte
 // offset in an SGPR (plane and variable) and a loop-invariant per-thread
@@ -96,10 +107,12 @@ __device__ __forceinline__ void load_cell_raw(const StageArgs& A, __amdgpu_buffe
 
 // FP64 cell state from its stored values: widening and background (FP32
 // perturbation form, b its index), then the mirror negation of momentum
-// component `negv` (>= 0) for a ghost across a wall.
+// component `negv` (>= 0) for a ghost across a wall, and for a hydrostatic
+// wall's ghost (lever = (x_g - x_k) g != 0) the energy of the carried
+// pressure, E + rho lever (de/dP)_rho (rho and |V| unchanged).
 template <int NDIM, typename ST>
 __device__ __forceinline__ void finish_cell(const StageArgs& A, const ST (&raw)[NDIM + 2], int negv, int b,
-                                            double (&u)[NDIM + 2]) {
+                                            double (&u)[NDIM + 2], double lever = 0.0) {
   constexpr int NV = NDIM + 2;
 #pragma unroll
   for (int v = 0; v < NV; ++v) u[v] = (double)raw[v];
@@ -118,6 +131,10 @@ __device__ __forceinline__ void finish_cell(const StageArgs& A, const ST (&raw)[
 #pragma unroll
   for (int v = 1; v <= NDIM; ++v)
     if (v == negv) u[v] = -u[v];
+  if (lever != 0.0) {
+    const double dedp = A.eos ? (1.0 - A.vdw_b * u[0]) * A.inv_gm1 : A.inv_gm1;
+    u[NDIM + 1] = u[NDIM + 1] + u[0] * lever * dedp;
+  }
 }
 
 // FP64 cell state from its stored values with the background values bgv
@@ -148,10 +165,11 @@ __device__ __forceinline__ void load_bg(__amdgpu_buffer_rsrc_t r, int nbg, int i
 // negate (mirror ghost); b: background index (FP32 perturbation form).
 template <int NDIM, typename ST>
 __device__ __forceinline__ void load_cell(const StageArgs& A, __amdgpu_buffer_rsrc_t r, int soff,
-                                          int voff, int negv, int b, double (&u)[NDIM + 2]) {
+                                          int voff, int negv, int b, double (&u)[NDIM + 2],
+                                          double lever = 0.0) {
   ST raw[NDIM + 2];
   load_cell_raw<NDIM, ST>(A, r, soff, voff, raw);
-  finish_cell<NDIM, ST>(A, raw, negv, b, u);
+  finish_cell<NDIM, ST>(A, raw, negv, b, u, lever);
 }
 
 // Index of the background profile for cell (i, j, k) in kernel axes.
@@ -241,6 +259,7 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
                                              int chunk_base, double dt, unsigned& bad) {
   constexpr int FORM = FORMX & 7;     // correction form
   constexpr int EXT = FORMX & (kExtCmax | kExtVdw);  // xi from eq. cx; van der Waals gas
+  constexpr bool HYD = (FORMX & kExtHydro) != 0;     // hydrostatic walls (y, march axis)
   constexpr int NV = NDIM + 2;
   constexpr int PL = NV + 3;          // face payload: U, P, c_tot, V_normal
   constexpr bool HS = (NDIM == 3);    // stacked y rows
@@ -323,9 +342,18 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
   // y rows just outside the tile (3D): columns and mirror flags, once
   int clo1 = 0, clo2 = 0, chi1 = 0, chi2 = 0, nlo1 = -1, nlo2 = -1, nhi1 = -1, nhi2 = -1;
   int blo1 = 0, blo2 = 0, bhi1 = 0, bhi2 = 0;
+  double llo1 = 0.0, llo2 = 0.0, lhi1 = 0.0, lhi2 = 0.0;  // hydrostatic wall levers
   if constexpr (HS) {
     bool n;
     int jj;
+    if constexpr (HYD) {
+      const double dy = A.dx[1], gy = A.g[1];
+      const int bl = A.bc_lo[1], bh = A.bc_hi[1];
+      llo1 = hydro_lever(j0 - 1, G.ns, bl, bh, dy, gy);
+      llo2 = hydro_lever(j0 - 2, G.ns, bl, bh, dy, gy);
+      lhi1 = hydro_lever(j0 + ts_eff, G.ns, bl, bh, dy, gy);
+      lhi2 = hydro_lever(j0 + ts_eff + 1, G.ns, bl, bh, dy, gy);
+    }
     jj = map_index(j0 - 1, G.ns, A.bc_lo[1], A.bc_hi[1], n); nlo1 = n ? 2 : -1; clo1 = (jj * G.nx + i) * SZ;
     blo1 = (A.bg_axis == 1) ? jj : bgi_xy;
     jj = map_index(j0 - 2, G.ns, A.bc_lo[1], A.bc_hi[1], n); nlo2 = n ? 2 : -1; clo2 = (jj * G.nx + i) * SZ;
@@ -346,6 +374,7 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
   const int oc1 = o_lo ? clo1 : chi1, oc2 = o_lo ? clo2 : chi2;
   const int on1 = o_lo ? nlo1 : nhi1, on2 = o_lo ? nlo2 : nhi2;
   const int ob1 = o_lo ? blo1 : bhi1, ob2 = o_lo ? blo2 : bhi2;
+  const double ol1 = o_lo ? llo1 : lhi1, ol2 = o_lo ? llo2 : lhi2;
   ST o1[NV], o2[NV], o3[ONE ? NV : 1], o4[ONE ? NV : 1];  // stored values, finished at use
 
   double q0[NV], q1[NV], sm0[NV], Fm_lo[NV];
@@ -357,12 +386,15 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
     bool n;
     int kk;
     kk = map_index(k0l - 2, G.nm, rm_lo, rm_hi, n);
-    load_cell<NDIM, ST>(A, uin, kk * plane, col, n ? NDIM : -1, bgk(kk), qa);
+    load_cell<NDIM, ST>(A, uin, kk * plane, col, n ? NDIM : -1, bgk(kk), qa,
+                        HYD ? hydro_lever(k0l - 2, G.nm, rm_lo, rm_hi, A.dx[am], A.g[am]) : 0.0);
     kk = map_index(k0l - 1, G.nm, rm_lo, rm_hi, n);
-    load_cell<NDIM, ST>(A, uin, kk * plane, col, n ? NDIM : -1, bgk(kk), qb);
+    load_cell<NDIM, ST>(A, uin, kk * plane, col, n ? NDIM : -1, bgk(kk), qb,
+                        HYD ? hydro_lever(k0l - 1, G.nm, rm_lo, rm_hi, A.dx[am], A.g[am]) : 0.0);
     load_cell<NDIM, ST>(A, uin, k0l * plane, col, -1, bgk(k0l), q0);
     kk = map_index(k0l + 1, G.nm, rm_lo, rm_hi, n);
-    load_cell<NDIM, ST>(A, uin, kk * plane, col, n ? NDIM : -1, bgk(kk), q1);
+    load_cell<NDIM, ST>(A, uin, kk * plane, col, n ? NDIM : -1, bgk(kk), q1,
+                        HYD ? hydro_lever(k0l + 1, G.nm, rm_lo, rm_hi, A.dx[am], A.g[am]) : 0.0);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       ha[v] = mc_half(qb[v] - qa[v], q0[v] - qb[v]);
@@ -394,10 +426,12 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
     // this plane's work)
     ST q2r[NV], unr[NV];
     int q2k = 0, q2neg = -1;
+    double q2lev = 0.0;
     if constexpr (HM) {
       bool n;
       q2k = map_index(min(kraw, G.nm - 1) + 2, G.nm, rm_lo, rm_hi, n);
       q2neg = n ? NDIM : -1;
+      if constexpr (HYD) q2lev = hydro_lever(min(kraw, G.nm - 1) + 2, G.nm, rm_lo, rm_hi, A.dx[am], A.g[am]);
       load_cell_raw<NDIM, ST>(A, uin, q2k * plane, col, q2r);
     }
     if constexpr (STAGE == 2) load_cell_raw<NDIM, ST, HS ? RSST_UN_AUX : 0>(A, unp, koff, col, unr);
@@ -484,9 +518,9 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
       double uD[NV], uU[NV], h[NV];
       if (first_row && pre) {
         if (F32 && !bg_rows) finish_cell_bgv<NDIM, ST>(o1, on1, bgA, uD);
-        else finish_cell<NDIM, ST>(A, o1, on1, bg_on_m ? k : ob1, uD);
+        else finish_cell<NDIM, ST>(A, o1, on1, bg_on_m ? k : ob1, uD, ol1);
       } else if (first_row) {
-        load_cell<NDIM, ST>(A, uin, koff, clo1, nlo1, bg_on_m ? k : blo1, uD);
+        load_cell<NDIM, ST>(A, uin, koff, clo1, nlo1, bg_on_m ? k : blo1, uD, llo1);
       } else {
 #pragma unroll
         for (int v = 0; v < NV; ++v) uD[v] = Urow[(v * TS + row - 1) * nxp + i_raw];
@@ -494,13 +528,13 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
       if (last_row && pre) {
         if constexpr (ONE) {
           if (F32 && !bg_rows) finish_cell_bgv<NDIM, ST>(o3, nhi1, bgA, uU);
-          else finish_cell<NDIM, ST>(A, o3, nhi1, bg_on_m ? k : bhi1, uU);
+          else finish_cell<NDIM, ST>(A, o3, nhi1, bg_on_m ? k : bhi1, uU, lhi1);
         } else {
           if (F32 && !bg_rows) finish_cell_bgv<NDIM, ST>(o1, on1, bgA, uU);
-          else finish_cell<NDIM, ST>(A, o1, on1, bg_on_m ? k : ob1, uU);
+          else finish_cell<NDIM, ST>(A, o1, on1, bg_on_m ? k : ob1, uU, ol1);
         }
       } else if (last_row) {
-        load_cell<NDIM, ST>(A, uin, koff, chi1, nhi1, bg_on_m ? k : bhi1, uU);
+        load_cell<NDIM, ST>(A, uin, koff, chi1, nhi1, bg_on_m ? k : bhi1, uU, lhi1);
       } else {
         const int ru = min(row + 1, TS - 1);  // idle rows past the tile read in range
 #pragma unroll
@@ -519,13 +553,13 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
           if (pre) {
             if constexpr (ONE) {
               if (F32 && !bg_rows) finish_cell_bgv<NDIM, ST>(o4, nhi2, bgA, u2);
-              else finish_cell<NDIM, ST>(A, o4, nhi2, bg_on_m ? k : bhi2, u2);
+              else finish_cell<NDIM, ST>(A, o4, nhi2, bg_on_m ? k : bhi2, u2, lhi2);
             } else {
               if (F32 && !bg_rows) finish_cell_bgv<NDIM, ST>(o2, on2, bgA, u2);
-              else finish_cell<NDIM, ST>(A, o2, on2, bg_on_m ? k : ob2, u2);
+              else finish_cell<NDIM, ST>(A, o2, on2, bg_on_m ? k : ob2, u2, ol2);
             }
           } else {
-            load_cell<NDIM, ST>(A, uin, koff, chi2, nhi2, bg_on_m ? k : bhi2, u2);
+            load_cell<NDIM, ST>(A, uin, koff, chi2, nhi2, bg_on_m ? k : bhi2, u2, lhi2);
           }
 #pragma unroll
           for (int v = 0; v < NV; ++v) hh[v] = mc_half(uU[v] - q0[v], u2[v] - uU[v]);
@@ -544,9 +578,9 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
         double u2[NV], hh[NV], Fh[NV];
         if (pre) {
           if (F32 && !bg_rows) finish_cell_bgv<NDIM, ST>(o2, on2, bgA, u2);
-          else finish_cell<NDIM, ST>(A, o2, on2, bg_on_m ? k : ob2, u2);
+          else finish_cell<NDIM, ST>(A, o2, on2, bg_on_m ? k : ob2, u2, ol2);
         } else {
-          load_cell<NDIM, ST>(A, uin, koff, clo2, nlo2, bg_on_m ? k : blo2, u2);
+          load_cell<NDIM, ST>(A, uin, koff, clo2, nlo2, bg_on_m ? k : blo2, u2, llo2);
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v) hh[v] = mc_half(uD[v] - u2[v], q0[v] - uD[v]);
@@ -635,7 +669,7 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
     double q2[NV];
     if constexpr (HM) {
       if constexpr (F32) finish_cell_bgv<NDIM, ST>(q2r, q2neg, bg_on_m ? bgB : bgA, q2);
-      else finish_cell<NDIM, ST>(A, q2r, q2neg, bgk(q2k), q2);
+      else finish_cell<NDIM, ST>(A, q2r, q2neg, bgk(q2k), q2, q2lev);
       double sm1[NV], Fm_hi[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) sm1[v] = mc_half(q1[v] - q0[v], q2[v] - q1[v]);

@@ -16,7 +16,7 @@
 namespace rsstk {
 
 // FORM: the correction form, plus kExtCmax when xi follows the sound speed
-// (eq. cx) or kExtVdw for the van der Waals gas.
+// (eq. cx), kExtVdw for the van der Waals gas, kExtHydro for hydrostatic walls.
 #ifndef RSST_LB3
 #define RSST_LB3 512
 #endif
@@ -88,16 +88,29 @@ static hipError_t launch_stage_x(const StageArgs& a, hipStream_t s) {
   }
 }
 
-// The van der Waals kernels exist for FP64 storage only (the C ABI rejects
-// the other combinations before any launch).
+// The van der Waals and hydrostatic-wall kernels exist for FP64 storage only
+// (the C ABI rejects the other combinations before any launch); 1D grids
+// need no hydrostatic variant (their walls are x walls, allowed only without
+// a force along x, where they are mirror walls).
+template <int NDIM, int STAGE, typename ST, int H>
+static hipError_t launch_stage_g(const StageArgs& a, hipStream_t s) {
+  if (a.eos) return launch_stage_x<NDIM, STAGE, ST, kExtVdw | H>(a, s);
+  return a.inv_cmax2 > 0.0 ? launch_stage_x<NDIM, STAGE, ST, kExtCmax | H>(a, s)
+                           : launch_stage_x<NDIM, STAGE, ST, H>(a, s);
+}
+
 template <int NDIM, int STAGE, typename ST>
 static hipError_t launch_stage_f(const StageArgs& a, hipStream_t s) {
   if constexpr (sizeof(ST) == 8) {
-    if (a.eos) return launch_stage_x<NDIM, STAGE, ST, kExtVdw>(a, s);
+    if constexpr (NDIM >= 2) {
+      if (a.hydro) return launch_stage_g<NDIM, STAGE, ST, kExtHydro>(a, s);
+    }
+    return launch_stage_g<NDIM, STAGE, ST, 0>(a, s);
+  } else {
+    if (a.eos || a.hydro) return hipErrorInvalidValue;
+    return a.inv_cmax2 > 0.0 ? launch_stage_x<NDIM, STAGE, ST, kExtCmax>(a, s)
+                             : launch_stage_x<NDIM, STAGE, ST, 0>(a, s);
   }
-  if (a.eos) return hipErrorInvalidValue;
-  return a.inv_cmax2 > 0.0 ? launch_stage_x<NDIM, STAGE, ST, kExtCmax>(a, s)
-                           : launch_stage_x<NDIM, STAGE, ST, 0>(a, s);
 }
 
 template <int NDIM, typename ST>

@@ -130,6 +130,26 @@ def test_vdw_combinations_unsupported_on_host():
     assert not h.value
 
 
+def test_hydro_wall_combinations_on_host():
+    """Hydrostatic walls: FP64 without the adjoint, and on x only without a
+    force along x; everything else is reported before any device call."""
+    h = ctypes.c_void_p()
+    cfg = W.base_cfg(2, [16, 12], bc_lo=["periodic", "hydro"], g=[0.0, -1.0])
+    c = R.make_config(cfg, prec="fp32_pert", bg=None)
+    c.bg = ctypes.c_void_p(8)  # never dereferenced
+    assert R.lib().rsst_init(ctypes.byref(c), None, ctypes.byref(h)) == -4
+    c = R.make_config(cfg, adjoint=True)
+    assert R.lib().rsst_init(ctypes.byref(c), None, ctypes.byref(h)) == -4
+    c = R.make_config(W.base_cfg(2, [16, 12], bc_lo=["hydro", "periodic"], g=[0.5, 0.0]))
+    assert R.lib().rsst_init(ctypes.byref(c), None, ctypes.byref(h)) == -4
+    c = R.make_config(W.base_cfg(1, [16], bc_lo=["hydro"], g=[-1.0]))
+    assert R.lib().rsst_init(ctypes.byref(c), None, ctypes.byref(h)) == -4
+    c = R.make_config(cfg)
+    c.bc_hi[1] = 3
+    assert R.lib().rsst_init(ctypes.byref(c), None, ctypes.byref(h)) == -1
+    assert not h.value
+
+
 def test_null_arguments():
     L = R.lib()
     assert L.rsst_adjoint_step(None, None, None, ctypes.c_double(0.1), None, None) == -1

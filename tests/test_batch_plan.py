@@ -172,3 +172,10 @@ def test_batch_takes_ideal_gas_boxes_only():
     with pytest.raises(rs.RsstError) as e:
         rs.rsst_batch_plan(cfgs, [16, 16, 16, 16])
     assert e.value.code == -4  # RSST_E_UNSUPPORTED
+
+
+def test_batch_takes_no_hydrostatic_walls():
+    cfgs = [_cfg(16, 12), _cfg(20, 16, ybc="hydro")]
+    with pytest.raises(rs.RsstError) as e:
+        rs.rsst_batch_plan(cfgs, [16, 16, 16, 16])
+    assert e.value.code == -4  # RSST_E_UNSUPPORTED
