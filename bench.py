@@ -365,6 +365,20 @@ def main():
     eff = 5 * nv * 8 * ncell / (ms_step * 1e-3) / 1e9
     version = R.rsst_version()
     traffic = traffic_from_profile("stage2_strat3d_256_fp64", version)
+    # a plain device copy of one 256^3 FP64 state (read + write), the second
+    # denominator next to the published HBM peak
+    xa = torch.empty(nv * ncell, dtype=torch.float64, device=dev).fill_(1.0)
+    xb = torch.empty_like(xa)
+    for _ in range(3):
+        xb.copy_(xa)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(10):
+        xb.copy_(xa)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * xa.numel() * 8 * 10 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del xa, xb
 
     out = {
         "metric": METRIC,
@@ -385,7 +399,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(ach2, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(ach2 / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": "stage_kernel<3,2,double> (RK stage 2)",
-                     "alg_bytes_per_launch": bytes_s2, "avg_ms": round(s2, 5)},
+                     "alg_bytes_per_launch": bytes_s2, "avg_ms": round(s2, 5),
+                     "copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(ach2 / copy_gbs, 4),
+                     "traffic_GBs": round(traffic / (s2 * 1e-3) / 1e9, 1) if traffic else None},
         "stage1": {"avg_ms": round(s1, 5), "achieved_GBs": round(ach1, 1),
                    "alg_bytes_per_launch": bytes_s1},
         "effective_GBs_step": round(eff, 1),
@@ -579,8 +595,14 @@ def main():
         oracle.run(cfg1, U1c, 1)
         one_s = time.perf_counter() - t1
         oracle.set_threads(nth)
+        model = ""
+        try:
+            with open("/proc/cpuinfo") as f:
+                model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+        except OSError:
+            pass
         out["cpu_baseline"] = {"value": round(ncell * args.cpu_steps / cpu_s / 1e9, 6),
-                               "unit": "Gcell-updates/s", "cores": nth,
+                               "unit": "Gcell-updates/s", "cores": nth, "cpu_model": model,
                                "kind": "oracle",
                                "sample": f"{args.cpu_steps} full steps of the 256^3 box "
                                          f"({cpu_s:.1f} s)",
