@@ -47,6 +47,32 @@ def traffic_from_profile(kernel_tag: str, version: str):
     return d.get("bytes_per_launch")
 
 
+def alu_view(version: str, value: float):
+    """The FP64-ALU side of the headline kernels from the committed SQ counter
+    summary (if taken on this revision): VALU wave-instructions per
+    cell-update (both stages) and the rate at which they would fill every
+    SIMD's issue slots (one wave64 instruction per 4 cycles, 1024 SIMDs at
+    2.4 GHz); frac = value / that ceiling."""
+    path = os.path.join(ROOT, "profiles", "stage_kernels_strat3d_256_sq_counters.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    if f"`{version}`" not in text:
+        return None
+    per = {}
+    for line in text.splitlines():
+        for st in (1, 2):
+            if line.startswith(f"| `void stage_kernel<3, {st}, double, 1, 4>"):
+                per[st] = float(line.split("|")[2])
+    if len(per) != 2:
+        return None
+    wi = per[1] + per[2]
+    ceiling = 1024 * 2.4e9 / 4 / wi / 1e9
+    return {"bound": "alu", "valu_wave_instr_per_cell_update": round(wi, 2),
+            "ceiling_Gcell_updates_s": round(ceiling, 2), "frac": round(value / ceiling, 4),
+            "source": "profiles/stage_kernels_strat3d_256_sq_counters.md"}
+
+
 def pert_err(Ug, pert, nv):
     """Max error over the perturbation scale per variable; the momentum
     components share the largest momentum scale."""
@@ -401,7 +427,8 @@ def main():
                      "traffic": traffic, "kernel": "stage_kernel<3,2,double> (RK stage 2)",
                      "alg_bytes_per_launch": bytes_s2, "avg_ms": round(s2, 5),
                      "copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(ach2 / copy_gbs, 4),
-                     "traffic_GBs": round(traffic / (s2 * 1e-3) / 1e9, 1) if traffic else None},
+                     "traffic_GBs": round(traffic / (s2 * 1e-3) / 1e9, 1) if traffic else None,
+                     "alu_view": alu_view(version, gcell)},
         "stage1": {"avg_ms": round(s1, 5), "achieved_GBs": round(ach1, 1),
                    "alg_bytes_per_launch": bytes_s1},
         "effective_GBs_step": round(eff, 1),
