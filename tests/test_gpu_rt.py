@@ -90,3 +90,27 @@ def test_rt_step_saving_and_growth():
           flush=True)
     assert n1 >= 4 * n6
     assert abs(v6 - v1) <= 0.1 * v1
+
+
+def test_rt_typical_mach_number_as_in_paper():
+    """Sec. 4.4 states the Mach number of the RT run without the RSST
+    (tests/golden/rt_typical_mach.json); at 128^2 with xi = 1 to t = 2.5 the
+    largest |V|/a at the end (the diagnostics' max xi|V|/a at xi = 1) is
+    within a factor of two of it."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "rt_typical_mach.json")))
+    cfg, U0, meta = W.rt2d(128, form="pvs", xi=1.0)
+    U = torch.from_numpy(U0).cuda()
+    s = R.Solver(cfg, t_end=meta["t_end"])
+    t = 0.0
+    for _ in range(200):  # chunks of steps until t_end (about 66 000 steps)
+        s.steps(U, 2000)
+        t, dt = s.time()
+        if dt == 0.0:
+            break
+    mach = float(s.diag(U)[7])
+    s.close()
+    print(f"[rt] xi=1 128^2 t={t} max |V|/a = {mach:.4f} (paper: about {gold['value']})", flush=True)
+    assert t == pytest.approx(meta["t_end"], rel=1e-13)
+    assert 0.5 * gold["value"] <= mach <= 2.0 * gold["value"]
