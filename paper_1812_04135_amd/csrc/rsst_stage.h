@@ -293,13 +293,21 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
   // workgroup) only take part in the barriers
   const bool wave_idle = w >= nwx * TS;
   const int row = wave_idle ? 0 : row_raw;  // idle waves read row 0's slots
-  const int j0 = HS ? tile_s * TS : 0;
+  // 3D: the tile stores rows [tile_s TS, tile_s TS + TS).  The last tile of a
+  // column whose height is not a multiple of TS is moved down to end at the
+  // last row: its rows below tile_s TS belong to the tile before it and are
+  // computed (the same bits, as every face is formed from the same face
+  // states) but not stored.  So a tile holds min(TS, ns) >= 2 rows whenever
+  // TS >= 2 (ns >= 4), and its first and last rows are distinct rows that
+  // both read their outside rows a plane ahead.
+  const int j_own = HS ? tile_s * TS : 0;
+  const int j0 = HS ? min(j_own, max(G.ns - TS, 0)) : 0;
   const int ts_eff = HS ? min(TS, G.ns - j0) : TS;
   const bool xin = i_raw < G.nx;
   const int chunk = HS ? chunk_base : chunk_base + row;
   const int k0 = chunk * G.km;
   const int k1 = min(k0 + G.km, G.nm);
-  const bool active = xin && row < ts_eff && k0 < G.nm && !wave_idle;
+  const bool active = xin && row < ts_eff && k0 < G.nm && !wave_idle && j0 + row >= j_own;
   const int i = xin ? i_raw : G.nx - 1;
   const int j = HS ? j0 + min(row, ts_eff - 1) : 0;
   const bool last_x = (i_raw == G.nx - 1);
@@ -366,10 +374,15 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
   // The edge rows read the two rows outside their side of the tile one
   // plane ahead, so their load latency hides behind a whole plane of work:
   // o1, o2 hold the near and far outside rows of the wave's side (one-row
-  // tiles, where a row is both edges: o1, o2 below and o3, o4 above).  A
-  // ragged one-row tile of a taller tile shape loads them when needed.
+  // tiles, where a row is both edges: o1, o2 below and o3, o4 above).  The
+  // rows between the edges issue the same loads (the rows above the tile,
+  // unused), so every wave has the same loads in flight at every point of
+  // the march: loads complete in order, and a wait sized for a wave with
+  // fewer loads in flight would make the edge rows wait for the loads of
+  // the next plane.  For the same reason no load inside the march is
+  // consumed in the phase that issues it.
   constexpr bool ONE = HS && TSC == 1;
-  const bool pre = HS && (ONE || first_row != last_row);
+  constexpr bool pre = HS;
   const bool o_lo = first_row;  // o1, o2 are the rows below (else above)
   const int oc1 = o_lo ? clo1 : chi1, oc2 = o_lo ? clo2 : chi2;
   const int on1 = o_lo ? nlo1 : nhi1, on2 = o_lo ? nlo2 : nhi2;
@@ -407,7 +420,7 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
   } else {
     load_cell<NDIM, ST>(A, uin, 0, col, -1, bgi_xy, q0);
   }
-  if (pre) {
+  if constexpr (pre) {
     load_cell_raw<NDIM, ST>(A, uin, k0l * plane, oc1, o1);
     load_cell_raw<NDIM, ST>(A, uin, k0l * plane, oc2, o2);
     if constexpr (ONE) {
@@ -516,16 +529,14 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
     Face<NV> fym;
     if constexpr (HS) {
       double uD[NV], uU[NV], h[NV];
-      if (first_row && pre) {
+      if (first_row) {
         if (F32 && !bg_rows) finish_cell_bgv<NDIM, ST>(o1, on1, bgA, uD);
         else finish_cell<NDIM, ST>(A, o1, on1, bg_on_m ? k : ob1, uD, ol1);
-      } else if (first_row) {
-        load_cell<NDIM, ST>(A, uin, koff, clo1, nlo1, bg_on_m ? k : blo1, uD, llo1);
       } else {
 #pragma unroll
         for (int v = 0; v < NV; ++v) uD[v] = Urow[(v * TS + row - 1) * nxp + i_raw];
       }
-      if (last_row && pre) {
+      if (last_row) {
         if constexpr (ONE) {
           if (F32 && !bg_rows) finish_cell_bgv<NDIM, ST>(o3, nhi1, bgA, uU);
           else finish_cell<NDIM, ST>(A, o3, nhi1, bg_on_m ? k : bhi1, uU, lhi1);
@@ -533,8 +544,6 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
           if (F32 && !bg_rows) finish_cell_bgv<NDIM, ST>(o1, on1, bgA, uU);
           else finish_cell<NDIM, ST>(A, o1, on1, bg_on_m ? k : ob1, uU, ol1);
         }
-      } else if (last_row) {
-        load_cell<NDIM, ST>(A, uin, koff, chi1, nhi1, bg_on_m ? k : bhi1, uU, lhi1);
       } else {
         const int ru = min(row + 1, TS - 1);  // idle rows past the tile read in range
 #pragma unroll
@@ -550,16 +559,12 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
           // minus state of the row above the tile, and the flux at the
           // tile's upper face
           double u2[NV], hh[NV], Fh[NV];
-          if (pre) {
-            if constexpr (ONE) {
-              if (F32 && !bg_rows) finish_cell_bgv<NDIM, ST>(o4, nhi2, bgA, u2);
-              else finish_cell<NDIM, ST>(A, o4, nhi2, bg_on_m ? k : bhi2, u2, lhi2);
-            } else {
-              if (F32 && !bg_rows) finish_cell_bgv<NDIM, ST>(o2, on2, bgA, u2);
-              else finish_cell<NDIM, ST>(A, o2, on2, bg_on_m ? k : ob2, u2, ol2);
-            }
+          if constexpr (ONE) {
+            if (F32 && !bg_rows) finish_cell_bgv<NDIM, ST>(o4, nhi2, bgA, u2);
+            else finish_cell<NDIM, ST>(A, o4, nhi2, bg_on_m ? k : bhi2, u2, lhi2);
           } else {
-            load_cell<NDIM, ST>(A, uin, koff, chi2, nhi2, bg_on_m ? k : bhi2, u2, lhi2);
+            if (F32 && !bg_rows) finish_cell_bgv<NDIM, ST>(o2, on2, bgA, u2);
+            else finish_cell<NDIM, ST>(A, o2, on2, bg_on_m ? k : ob2, u2, ol2);
           }
 #pragma unroll
           for (int v = 0; v < NV; ++v) hh[v] = mc_half(uU[v] - q0[v], u2[v] - uU[v]);
@@ -576,12 +581,8 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
         // plus state of the row below the tile, and the flux at the tile's
         // lower face
         double u2[NV], hh[NV], Fh[NV];
-        if (pre) {
-          if (F32 && !bg_rows) finish_cell_bgv<NDIM, ST>(o2, on2, bgA, u2);
-          else finish_cell<NDIM, ST>(A, o2, on2, bg_on_m ? k : ob2, u2, ol2);
-        } else {
-          load_cell<NDIM, ST>(A, uin, koff, clo2, nlo2, bg_on_m ? k : blo2, u2, llo2);
-        }
+        if (F32 && !bg_rows) finish_cell_bgv<NDIM, ST>(o2, on2, bgA, u2);
+        else finish_cell<NDIM, ST>(A, o2, on2, bg_on_m ? k : ob2, u2, ol2);
 #pragma unroll
         for (int v = 0; v < NV; ++v) hh[v] = mc_half(uD[v] - u2[v], q0[v] - uD[v]);
         Face<NV> fh;
@@ -591,7 +592,7 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
         for (int v = 0; v < NV; ++v) Frow[(v * 2) * nxp + i_raw] = Fh[v];
       }
     }
-    if (pre) {  // the outside rows of the next plane
+    if constexpr (pre) {  // the outside rows of the next plane
       const int kn = min(kraw + 1, G.nm - 1);
       load_cell_raw<NDIM, ST>(A, uin, kn * plane, oc1, o1);
       load_cell_raw<NDIM, ST>(A, uin, kn * plane, oc2, o2);

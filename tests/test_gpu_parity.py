@@ -214,14 +214,21 @@ def test_uniform_state_bitwise_3d():
     assert np.array_equal(Ug, U0)
 
 
-def test_translation_invariance_bitwise():
+@pytest.mark.parametrize("n,shift", [([100, 14, 12], (5, 3, 37)), ([256, 9, 6], (2, 1, 0)),
+                                     ([64, 13, 5], (1, 5, 3)), ([192, 7, 5], (3, 2, 70))])
+def test_translation_invariance_bitwise(n, shift):
     """A periodic shift that is not a multiple of any tile or wave moves the
-    result bit for bit (tile seams and halos compute the same numbers)."""
-    cfg, U0 = W.random_state(3, [100, 14, 12], seed_k=400, xi=3.0)
+    result bit for bit (tile seams and halos compute the same numbers).  The
+    y heights are not multiples of the tile heights (2, 4, 8 rows), so the
+    last tile of each column overlaps the one before it, and the rows it
+    computes without storing land on rows that another tile stores after the
+    shift."""
+    cfg, U0 = W.random_state(3, n, seed_k=400 + n[0], xi=3.0)
+    print(f"[case] translation {n} shift {shift}", flush=True)
     Ua, _, _, _ = gpu_run(cfg, U0, 3)
-    Us = np.ascontiguousarray(np.roll(U0, shift=(5, 3, 37), axis=(1, 2, 3)))
+    Us = np.ascontiguousarray(np.roll(U0, shift=shift, axis=(1, 2, 3)))
     Ub, _, _, _ = gpu_run(cfg, Us, 3)
-    assert np.array_equal(np.roll(Ua, shift=(5, 3, 37), axis=(1, 2, 3)), Ub)
+    assert np.array_equal(np.roll(Ua, shift=shift, axis=(1, 2, 3)), Ub)
 
 
 @pytest.mark.parametrize("form", ["dvs", "pd", "euler"])
