@@ -445,15 +445,16 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
       q2k = map_index(min(kraw, G.nm - 1) + 2, G.nm, rm_lo, rm_hi, n);
       q2neg = n ? NDIM : -1;
       if constexpr (HYD) q2lev = hydro_lever(min(kraw, G.nm - 1) + 2, G.nm, rm_lo, rm_hi, A.dx[am], A.g[am]);
-      load_cell_raw<NDIM, ST>(A, uin, q2k * plane, col, q2r);
     }
-    if constexpr (STAGE == 2) load_cell_raw<NDIM, ST, HS ? RSST_UN_AUX : 0>(A, unp, koff, col, unr);
+    // the background rows first: plane k's is used earliest (P2)
     if constexpr (F32) {
       if (bg_on_m) {
         load_bg<NV>(bgr, A.nbg, k, bgA);
         load_bg<NV>(bgr, A.nbg, q2k, bgB);
       }
     }
+    if constexpr (HM) load_cell_raw<NDIM, ST>(A, uin, q2k * plane, col, q2r);
+    if constexpr (STAGE == 2) load_cell_raw<NDIM, ST, HS ? RSST_UN_AUX : 0>(A, unp, koff, col, unr);
 
     // ---- P1: publish this plane's cell state
     if constexpr (HS) {
