@@ -125,15 +125,16 @@ enum rsst_flag {
 typedef struct rsst_solver* rsst_handle;
 
 /* Validates cfg on the host before touching the device (RSST_E_ARG on any
- * invalid field), then allocates the workspace (stage buffer, reduction
- * scalars) on the current device and zeroes the scalars on `stream`,
+ * invalid field), then allocates the workspace (stage buffer, scalars, one
+ * CFL maximum per stage-kernel workgroup) on the current device and zeroes the scalars on `stream`,
  * synchronising it before returning (so later calls may use any stream).
  * t starts at 0.  No allocation happens after this call. */
 int rsst_init(const rsst_config* cfg, void* stream, rsst_handle* out);
 
-/* Sets t = t0 and computes the CFL time step of state U on the device.
- * rsst_step calls this by itself on the first CFL step; call it again after
- * writing U from outside. */
+/* Sets t = t0 and records, on the device, the maxima of c_tot over U from
+ * which the next CFL step forms its dt.  rsst_step calls this by itself (t
+ * unchanged) on the first CFL step; call it again after writing U from
+ * outside.  Every step records the maxima of the state it leaves. */
 int rsst_prime(rsst_handle h, const void* U, double t0, void* stream);
 
 /* One SSP-RK2 step of U in place:
@@ -145,9 +146,10 @@ int rsst_prime(rsst_handle h, const void* U, double t0, void* stream);
 int rsst_step(rsst_handle h, void* U, double dt_fixed, void* stream);
 
 /* One Runge-Kutta stage of rsst_step, for callers that schedule or time the
- * two stages separately.  stage 1: U1 = U + dt R(U) into the library's stage
+ * two stages separately.  stage 1: forms the step's dt (a CFL step: from the
+ * recorded maxima, cut at t_end) and U1 = U + dt R(U) into the library's stage
  * buffer (U unchanged); stage 2: U <- (U + (U1 + dt R(U1))) / 2, advancing t
- * and the device CFL dt.  A stage 2 call must follow a stage 1 call on the
+ * and recording the maxima of c_tot over the new U.  A stage 2 call must follow a stage 1 call on the
  * same U and dt_fixed; rsst_step(h, U, dt, s) is stage 1 then stage 2.
  * RSST_E_ARG for any other stage number. */
 int rsst_stage(rsst_handle h, void* U, int stage, double dt_fixed, void* stream);
@@ -160,7 +162,9 @@ int rsst_stage(rsst_handle h, void* U, int stage, double dt_fixed, void* stream)
 int rsst_steps(rsst_handle h, void* U, int nsteps, double dt_fixed, void* stream);
 
 /* Synchronises the stream, then returns the time t and the dt the next CFL
- * step will use. */
+ * step will use (formed on the host from the recorded maxima by the same
+ * operations as on the device, so the same value; 0 before any state has
+ * been recorded). */
 int rsst_get_time(rsst_handle h, double* t, double* dt_next, void* stream);
 
 /* FP64 diagnostics of U, summed over cells in a fixed order (deterministic):

@@ -10,6 +10,7 @@
 #include <cstdint>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "rsst.h"
 #include "rsst_adjoint.h"
@@ -27,6 +28,7 @@ struct rsst_solver {
   size_t elem;       // bytes per stored value
   void* u1;          // stage buffer, owned
   double* scal;      // device scalars, owned
+  double* blkmax;    // per-workgroup maxima of c_tot of the current state, owned
   double* part;      // diag partials, owned
   double* diag_out;  // 8 doubles, owned
   int npart;
@@ -112,7 +114,7 @@ const char* rsst_strerror(int s) {
   }
 }
 
-const char* rsst_version(void) { return "rsst-gfx950 stage-v10"; }
+const char* rsst_version(void) { return "rsst-gfx950 stage-v11"; }
 
 int rsst_init(const rsst_config* cfg, void* stream, rsst_handle* out) {
   if (!out) return RSST_E_ARG;
@@ -173,10 +175,14 @@ int rsst_init(const rsst_config* cfg, void* stream, rsst_handle* out) {
   const size_t ubytes = (size_t)h->nv * h->ncell * h->elem;
   if (hipMalloc(&h->u1, ubytes) != hipSuccess) { delete h; return RSST_E_NOMEM; }
   const size_t nscal = rsstk::kNumScalars;
+  a.nblk = a.geo.ntile_s * a.geo.nchunk;
+  h->scal = h->blkmax = h->part = h->diag_out = nullptr;
   if (hipMalloc((void**)&h->scal, nscal * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&h->blkmax, (size_t)a.nblk * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&h->part, (size_t)h->npart * 8 * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&h->diag_out, 8 * sizeof(double)) != hipSuccess) {
-    (void)hipFree(h->u1); (void)hipFree(h->scal); (void)hipFree(h->part); (void)hipFree(h->diag_out);
+    (void)hipFree(h->u1); (void)hipFree(h->scal); (void)hipFree(h->blkmax); (void)hipFree(h->part);
+    (void)hipFree(h->diag_out);
     delete h;
     return RSST_E_NOMEM;
   }
@@ -191,11 +197,13 @@ int rsst_init(const rsst_config* cfg, void* stream, rsst_handle* out) {
   }
   // zeroed before any launch on any stream
   if (hipMemsetAsync(h->scal, 0, nscal * sizeof(double), s) != hipSuccess ||
+      hipMemsetAsync(h->blkmax, 0, (size_t)a.nblk * sizeof(double), s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess) {
     rsst_destroy(h);
     return RSST_E_DEVICE;
   }
   a.scal = h->scal;
+  a.blkmax = h->blkmax;
   h->primed = false;
   *out = h;
   return RSST_OK;
@@ -228,8 +236,9 @@ int rsst_stage(rsst_handle h, void* U, int stage, double dt_fixed, void* stream)
     a.uout = U;
   }
   if (rsstk::launch_stage(a, stage, s) != hipSuccess) return RSST_E_DEVICE;
-  // a fixed step leaves the device dt at dt_fixed: re-prime before a CFL step
-  if (stage == 2 && dt_fixed > 0.0) h->primed = false;
+  // stage 2 stores the maxima of the new state, from which the next CFL dt
+  // is formed (after a fixed step too)
+  if (stage == 2) h->primed = true;
   return RSST_OK;
 }
 
@@ -259,7 +268,7 @@ int rsst_steps(rsst_handle h, void* U, int nsteps, double dt_fixed, void* stream
     const hipError_t e = h->elem == sizeof(float) ? rsstk::launch_steps1d<float>(a1, a2, nsteps, s)
                                                   : rsstk::launch_steps1d<double>(a1, a2, nsteps, s);
     if (e != hipSuccess) return RSST_E_DEVICE;
-    if (dt_fixed > 0.0) h->primed = false;
+    h->primed = true;
     return RSST_OK;
   }
   for (int q = 0; q < nsteps; ++q) {
@@ -272,10 +281,21 @@ int rsst_steps(rsst_handle h, void* U, int nsteps, double dt_fixed, void* stream
 int rsst_get_time(rsst_handle h, double* t, double* dt_next, void* stream) {
   if (!h) return RSST_E_ARG;
   double v[2];
+  std::vector<double> bm((size_t)h->args.nblk);
   if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return RSST_E_DEVICE;
-  if (hipMemcpy(v, h->scal, 2 * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+  if (hipMemcpy(v, h->scal, 2 * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(bm.data(), h->blkmax, bm.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
     return RSST_E_DEVICE;
-  if (dt_next) *dt_next = v[rsstk::kDtCur];
+  // the dt the next stage 1 would form (same operations, so the same bits):
+  // cfl h / max c_tot, cut at t_end; 0 before any state has been seen
+  double m = 0.0;
+  for (double x : bm) m = std::fmax(m, x);
+  double dn = 0.0;
+  if (m > 0.0) {
+    dn = h->args.cfl_h / m;
+    if (h->args.t_end > 0.0) dn = std::fmin(dn, std::fmax(h->args.t_end - v[rsstk::kTime], 0.0));
+  }
+  if (dt_next) *dt_next = dn;
   if (t) *t = v[rsstk::kTime];
   return RSST_OK;
 }
@@ -310,6 +330,7 @@ int rsst_destroy(rsst_handle h) {
   (void)hipDeviceSynchronize();
   (void)hipFree(h->u1);
   (void)hipFree(h->scal);
+  (void)hipFree(h->blkmax);
   (void)hipFree(h->part);
   (void)hipFree(h->diag_out);
   if (h->adj_work) (void)hipFree(h->adj_work);

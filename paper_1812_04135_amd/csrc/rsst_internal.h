@@ -7,7 +7,8 @@
 
 namespace rsstk {
 
-// Device-side scalars of one solver, in one small allocation.
+// Device-side scalars of one solver, in one small allocation.  kDtCur: the
+// dt of the step in progress (formed by stage 1, read by stage 2); kTime: t.
 enum Scalar { kDtCur = 0, kTime = 1, kMaxBits = 2, kDone = 3, kFlags = 4, kNumScalars = 8 };
 
 // Launch geometry of the fused stage kernel.
@@ -40,6 +41,8 @@ struct StageArgs {
   double cfl_h;      // cfl * h, h from the dt rule
   double t_end;      // > 0: cut dt at t_end
   double* scal;      // device scalars
+  double* blkmax;    // [nblk] largest c_tot of the current state per stage-2 workgroup
+  int nblk;          // stage-kernel workgroups (ntile_s * nchunk)
   const void* uin;   // stage input (halo reads)
   const void* un;    // stage 2: state at the start of the step (pointwise)
   void* uout;        // stage output (stage 2: the same array as un, updated in place)

@@ -36,7 +36,9 @@ namespace rsstk {
 
 // ---------------------------------------------------------------- prime
 
-// CFL time step of a state: dt = cfl * h / max c_tot; also sets t = t0.
+// The largest c_tot of a state per stage-kernel workgroup slot (the grid has
+// one workgroup per slot, each taking a strided share of the cells), from
+// which the next stage 1 forms the CFL dt; with set_t, also t = t0.
 template <int NDIM, typename ST>
 __global__ void __launch_bounds__(256) prime_kernel(const StageArgs A, const ST* __restrict__ u,
                                                     double t0, int set_t) {
@@ -74,23 +76,8 @@ __global__ void __launch_bounds__(256) prime_kernel(const StageArgs A, const ST*
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = wm;
   __syncthreads();
   if (threadIdx.x == 0) {
-    const double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-    unsigned long long* mb = (unsigned long long*)(A.scal + kMaxBits);
-    unsigned long long* done = (unsigned long long*)(A.scal + kDone);
-    atomicMax(mb, (unsigned long long)__double_as_longlong(m));
-    __threadfence();
-    const unsigned long long prev = atomicAdd(done, 1ull);
-    if (prev == (unsigned long long)(gridDim.x - 1)) {
-      __threadfence();
-      const double cmx = __longlong_as_double((long long)atomicAdd(mb, 0ull));
-      const double t = set_t ? t0 : A.scal[kTime];
-      double dn = A.cfl_h / cmx;
-      if (A.t_end > 0.0) dn = fmin(dn, fmax(A.t_end - t, 0.0));
-      A.scal[kTime] = t;
-      A.scal[kDtCur] = dn;
-      atomicExch(mb, 0ull);
-      atomicExch(done, 0ull);
-    }
+    A.blkmax[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    if (set_t && blockIdx.x == 0) A.scal[kTime] = t0;
   }
 }
 
@@ -241,9 +228,7 @@ hipError_t launch_stage(const StageArgs& a, int stage, hipStream_t s) {
 template <typename ST>
 static hipError_t launch_prime_p(const StageArgs& a, const void* u, double t0, int set_t,
                                  hipStream_t s) {
-  long long nb = (a.ncell + 255) / 256;
-  if (nb > 2048) nb = 2048;
-  const dim3 grid((unsigned)nb), block(256);
+  const dim3 grid((unsigned)a.nblk), block(256);
   switch (a.geo.ndim) {
     case 1: hipLaunchKernelGGL((prime_kernel<1, ST>), grid, block, 0, s, a, (const ST*)u, t0, set_t); break;
     case 2: hipLaunchKernelGGL((prime_kernel<2, ST>), grid, block, 0, s, a, (const ST*)u, t0, set_t); break;

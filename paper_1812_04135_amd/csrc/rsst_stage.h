@@ -723,8 +723,30 @@ __device__ __forceinline__ int xcd_tile(int b, int nblk) {
   return ((nblk & 7) == 0) ? (b & 7) * (nblk >> 3) + (b >> 3) : b;
 }
 
-// Workgroup maximum of c_tot, one atomic per workgroup; the last workgroup
-// to finish advances t and sets the next CFL dt (stage 2).
+// CFL step from the maxima of c_tot that the last stage 2 (or the prime
+// kernel) stored per workgroup: dt = cfl h / max, cut at t_end.  Formed by
+// every workgroup of stage 1 at its start, the same bits in each (a maximum
+// does not depend on its order).  Includes a workgroup barrier; red is not
+// written again in stage 1.
+__device__ __forceinline__ double cfl_dt_from_blocks(const StageArgs& A, double* red) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double m = 0.0;
+  for (int b = threadIdx.x; b < A.nblk; b += blockDim.x) m = fmax(m, A.blkmax[b]);
+  m = wave_max(m);
+  if (lane == 0) red[w] = m;
+  __syncthreads();
+  m = 0.0;
+  for (int q = 0; q < (int)(blockDim.x >> 6); ++q) m = fmax(m, red[q]);
+  const double t = A.scal[kTime];
+  double dt = A.cfl_h / m;
+  if (A.t_end > 0.0) dt = fmin(dt, fmax(A.t_end - t, 0.0));
+  return dt;
+}
+
+// Stage 2: the workgroup's largest c_tot of the new state, stored in its own
+// slot (plain store: the next stage 1 reads the slots after this kernel has
+// ended), and workgroup 0 advances t by the step's dt (t is read by no other
+// workgroup of this kernel).
 __device__ __forceinline__ void cfl_epilogue(const StageArgs& A, double* red, double cmax, double dt) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const double wm = wave_max(cmax);
@@ -733,25 +755,8 @@ __device__ __forceinline__ void cfl_epilogue(const StageArgs& A, double* red, do
   if (threadIdx.x == 0) {
     double m = 0.0;
     for (int q = 0; q < (int)(blockDim.x >> 6); ++q) m = fmax(m, red[q]);
-    unsigned long long* mb = (unsigned long long*)(A.scal + kMaxBits);
-    unsigned long long* done = (unsigned long long*)(A.scal + kDone);
-    atomicMax(mb, (unsigned long long)__double_as_longlong(m));
-    __threadfence();
-    const unsigned long long prev = atomicAdd(done, 1ull);
-    if (prev == (unsigned long long)(gridDim.x - 1)) {
-      __threadfence();
-      const double cm = __longlong_as_double((long long)atomicAdd(mb, 0ull));
-      const double t = A.scal[kTime] + dt;
-      double dn = dt;
-      if (A.dt_fixed <= 0.0) {
-        dn = A.cfl_h / cm;
-        if (A.t_end > 0.0) dn = fmin(dn, fmax(A.t_end - t, 0.0));
-      }
-      A.scal[kTime] = t;
-      A.scal[kDtCur] = dn;
-      atomicExch(mb, 0ull);
-      atomicExch(done, 0ull);
-    }
+    A.blkmax[blockIdx.x] = m;
+    if (blockIdx.x == 0) A.scal[kTime] = A.scal[kTime] + dt;
   }
 }
 

@@ -32,14 +32,22 @@ __global__ void __launch_bounds__(NDIM == 3 ? RSST_LB3 : 1024)
   const int L = xcd_tile(blockIdx.x, gridDim.x);
   const int tile_s = L % G.ntile_s;
   const int chunk_base = (L / G.ntile_s) * (NDIM == 3 ? 1 : G.ts);
-  const double dt = (A.dt_fixed > 0.0) ? A.dt_fixed : A.scal[kDtCur];
+  const Carve C = carve(NDIM, NDIM == 3 ? tile_rows(NWXC) : G.ts, NDIM == 3 ? NWXC : G.nwx);
+  // a CFL step's dt: formed by stage 1 from the maxima of the state it
+  // reads, recorded for stage 2
+  double dt = A.dt_fixed;
+  if (!(A.dt_fixed > 0.0)) {
+    if constexpr (STAGE == 1) {
+      dt = cfl_dt_from_blocks(A, lds + C.red);
+      if (blockIdx.x == 0 && threadIdx.x == 0) A.scal[kDtCur] = dt;
+    } else {
+      dt = A.scal[kDtCur];
+    }
+  }
   unsigned bad = 0;
   const double cmax = stage_body<NDIM, STAGE, ST, FORM, NWXC>(A, lds, tile_s, chunk_base, dt, bad);
   if (bad) atomicOr((unsigned*)(A.scal + kFlags), bad);
-  if constexpr (STAGE == 2) {
-    const Carve C = carve(NDIM, NDIM == 3 ? tile_rows(NWXC) : G.ts, NDIM == 3 ? NWXC : G.nwx);
-    cfl_epilogue(A, lds + C.red, cmax, dt);
-  }
+  if constexpr (STAGE == 2) cfl_epilogue(A, lds + C.red, cmax, dt);
 }
 
 template <int NDIM, int STAGE, typename ST, int FORM, int NWXC>
@@ -124,9 +132,11 @@ template hipError_t launch_stage_n<RSST_INST_NDIM, RSST_INST_ST>(const StageArgs
 // nsteps whole steps of a 1D grid in one launch.  A 1D grid is one workgroup
 // (a row of at most 16 waves), so both stages and the CFL maximum of every
 // step run in that workgroup with barriers in between: the stage bodies are
-// those of stage_kernel, the maximum and the next dt are formed as its
-// epilogue forms them, and t and dt stay in registers, so the state, t and dt
-// after each step are bitwise those of the per-stage launches.  Each lane
+// those of stage_kernel, each step's dt is formed from the previous step's
+// maximum as stage 1 forms it from the stored maxima, and t and dt stay in
+// registers (t and the last maximum are stored at the end), so the state, t
+// and the next dt after each step are bitwise those of the per-stage
+// launches.  Each lane
 // reads back only its own cell between the stages (neighbours come by DPP and
 // LDS), and the workgroup barrier orders those stores and loads.  With a CFL
 // step and an end time, the steps after t reaches t_end (dt = 0, which would
@@ -138,8 +148,13 @@ __global__ void __launch_bounds__(1024) steps1d_kernel(const StageArgs a1, const
   double* red = lds + carve(1, G.ts, G.nwx).red;
   const bool cfl = !(a1.dt_fixed > 0.0);
   double t = a1.scal[kTime];
-  double dt = cfl ? a1.scal[kDtCur] : a1.dt_fixed;
+  double dt = a1.dt_fixed;
+  if (cfl) {  // from the one stored maximum (a 1D grid is one workgroup), as stage 1 forms it
+    dt = a1.cfl_h / a1.blkmax[0];
+    if (a1.t_end > 0.0) dt = fmin(dt, fmax(a1.t_end - t, 0.0));
+  }
   unsigned bad = 0;
+  double mlast = -1.0;
   for (int q = 0; q < nsteps; ++q) {
     if (cfl && a1.t_end > 0.0 && !(dt > 0.0)) break;
     stage_body<1, 1, ST, FORM, 0>(a1, lds, 0, 0, dt, bad);
@@ -150,6 +165,7 @@ __global__ void __launch_bounds__(1024) steps1d_kernel(const StageArgs a1, const
     __syncthreads();
     double m = 0.0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, red[w]);
+    mlast = m;
     t = t + dt;
     if (cfl) {
       dt = a1.cfl_h / m;
@@ -160,7 +176,7 @@ __global__ void __launch_bounds__(1024) steps1d_kernel(const StageArgs a1, const
   if (bad) atomicOr((unsigned*)(a1.scal + kFlags), bad);
   if (threadIdx.x == 0) {
     a1.scal[kTime] = t;
-    a1.scal[kDtCur] = dt;
+    if (mlast >= 0.0) a1.blkmax[0] = mlast;  // the maximum of the state left in U
   }
 }
 
