@@ -191,18 +191,20 @@ Geometry plan_geometry(int ndim, const int n[3]) {
   if (ndim == 1) {
     G.km = 1;
   } else {
-    // chunks of 8 (2D: 2) to 128 planes (each chunk re-reads 4 planes and forms one
-    // extra face to start its march), halved while the grid has fewer
-    // workgroups than the 256 CUs (3D: one workgroup fills a CU) or than
-    // two per CU (2D rows of fewer waves); RSST_KM overrides the chunk
-    // length (tuning)
+    // chunks of 1 to 128 planes (3D; 2D: 64), halved while the grid has
+    // fewer workgroups than the 256 CUs (3D: one workgroup fills a CU) or
+    // than two per CU (2D rows of fewer waves).  A plane costs a workgroup
+    // about a microsecond and a half however few cells it holds (a wave runs
+    // ~1000 dependent instructions per plane), so a small grid is fastest as
+    // many short marches, although each chunk re-reads 4 planes and forms one
+    // extra face to start; RSST_KM overrides the chunk length (tuning)
     const long long want = ndim == 3 ? 256 : 512;
     int km = ndim == 3 ? 128 : 64;
-    const int kmin = ndim == 3 ? 8 : 2;  // 2D grids of few rows trade march starts for workgroups
+    const int kmin = 1;
     while (km > kmin && (long long)G.ntile_s * ((G.nm + km - 1) / km) < want) km >>= 1;
     if (const char* e = getenv("RSST_KM")) {
       const int v = atoi(e);
-      if (v >= 2 && v <= 4096) km = v;
+      if (v >= 1 && v <= 4096) km = v;
     }
     G.km = km < G.nm ? km : G.nm;
   }
