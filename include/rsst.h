@@ -71,7 +71,7 @@ typedef struct rsst_config {
   int n[3];          /* cells per axis (>= 4 on the used axes); axes >= ndim
                         must be 1.  Supported (else RSST_E_UNSUPPORTED): a
                         workgroup holds whole x rows, so n[0] <= 1024 in 1D
-                        and 2D and n[0] <= 256 in 3D; kernels address a state
+                        and 2D and n[0] <= 512 in 3D; kernels address a state
                         with 32-bit byte offsets, so nvar * ncell * (8 FP64,
                         4 FP32_PERT) < 2^31, e.g. 3D FP64 up to 53.6 M cells
                         (256 x 256 x 819)                                     */

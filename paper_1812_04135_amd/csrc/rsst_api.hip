@@ -95,7 +95,7 @@ static int validate(const rsst_config* c) {
   if (c->ndim == 1 && c->n[0] > 1024) return RSST_E_UNSUPPORTED;
   if (c->ndim == 2 && c->n[0] > 1024) return RSST_E_UNSUPPORTED;
   if (c->ndim == 3) {
-    if (c->n[0] > 256) return RSST_E_UNSUPPORTED;
+    if (c->n[0] > 512) return RSST_E_UNSUPPORTED;
   }
   return RSST_OK;
 }

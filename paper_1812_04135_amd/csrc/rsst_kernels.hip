@@ -183,6 +183,9 @@ Geometry plan_geometry(int ndim, const int n[3]) {
   G.nm = (ndim == 3) ? n[2] : (ndim == 2 ? n[1] : 1);
   G.nwx = (G.nx + 63) / 64;
   if (ndim == 3) {
+    // 3D rows of 5-8 waves run as rows of 8 (the waves past the row's end
+    // compute on clamped cells and store nothing)
+    if (G.nwx > 4) G.nwx = 8;
     G.ts = tile_rows(G.nwx);
   } else {
     G.ts = 1;

@@ -240,11 +240,14 @@ __host__ __device__ inline Carve carve(int ndim, int ts, int nwx) {
   return c;
 }
 
-// Rows per 3D tile for a row of nwx waves (512 threads at most).
+// Rows per 3D tile for a row of nwx waves (512 threads at most).  Rows of
+// 257-512 cells run as rows of 8 waves, one row per tile.
 #ifndef RSST_TS_WIDE
 #define RSST_TS_WIDE 2
 #endif
-__host__ __device__ constexpr int tile_rows(int nwx) { return nwx == 1 ? 8 : (nwx == 2 ? 4 : RSST_TS_WIDE); }
+__host__ __device__ constexpr int tile_rows(int nwx) {
+  return nwx == 1 ? 8 : (nwx == 2 ? 4 : (nwx <= 4 ? RSST_TS_WIDE : 1));
+}
 
 // One stage of R over one tile (3D: TS stacked y rows of one z-chunk) or one
 // group of strips (1D/2D: row r of the workgroup marches chunk

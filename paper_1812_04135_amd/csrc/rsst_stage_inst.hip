@@ -77,7 +77,9 @@ static hipError_t launch_stage_t(const StageArgs& a, hipStream_t s) {
       case 1: return launch_stage_k<NDIM, STAGE, ST, FORM, 1>(a, s);
       case 2: return launch_stage_k<NDIM, STAGE, ST, FORM, 2>(a, s);
       case 3: return launch_stage_k<NDIM, STAGE, ST, FORM, 3>(a, s);
-      default: return launch_stage_k<NDIM, STAGE, ST, FORM, 4>(a, s);
+      case 4: return launch_stage_k<NDIM, STAGE, ST, FORM, 4>(a, s);
+      case 8: return launch_stage_k<NDIM, STAGE, ST, FORM, 8>(a, s);
+      default: return hipErrorInvalidValue;
     }
   } else {
     return launch_stage_k<NDIM, STAGE, ST, FORM, 0>(a, s);

@@ -85,14 +85,15 @@ def test_fp32_perturbation_needs_background():
 
 
 def test_unsupported_shape_reported():
-    cfg, _ = W.random_state(3, [300, 8, 8])
+    cfg, _ = W.random_state(3, [513, 8, 8])
     c = R.make_config(cfg)
     h = ctypes.c_void_p()
     assert R.lib().rsst_init(ctypes.byref(c), None, ctypes.byref(h)) == -4
     # rows wider than one workgroup, and fields past 2 GiB (32-bit byte
     # offsets), are reported on the host; the largest supported ones pass
     # validation up to the device allocation (not attempted here)
-    for n, ok in (([1025], False), ([1025, 8], False), ([256, 256, 819], True), ([256, 256, 820], False)):
+    for n, ok in (([1025], False), ([1025, 8], False), ([256, 256, 819], True), ([256, 256, 820], False),
+                  ([512, 8, 8], True), ([513, 8, 8], False)):
         cfg = W.base_cfg(len(n), n)
         c = R.make_config(cfg)
         code = R.lib().rsst_init(ctypes.byref(c), None, ctypes.byref(h))

@@ -102,6 +102,8 @@ CASES = [
     (3, [17, 6, 5], ["reflect", "periodic", "periodic"], None, "dms"),
     (3, [256, 4, 4], ["periodic"] * 3, [0.0, 0.0, -0.5], "pd"),
     (3, [40, 10, 7], ["reflect"] * 3, None, "euler"),
+    (3, [300, 5, 6], ["periodic", "reflect", "reflect"], [0.0, 0.3, -0.5], "pvs"),  # 5 of 8 waves
+    (3, [512, 4, 5], ["reflect", "periodic", "periodic"], None, "pms"),  # widest 3D row
 ]
 
 
@@ -175,8 +177,9 @@ def test_strat3d_full_size_one_step_from_evolved_state():
     assert_parity(Ug, Uo, 3, what="strat3d 256^3 one step")
 
 
-def test_fp32_perturbation_matches_fp64_oracle_3d():
-    cfg, U0, meta = W.strat3d(n=32, nz=24, ny=16, xi=30.0)
+@pytest.mark.parametrize("n,ny,nz", [(32, 16, 24), (300, 5, 8)])
+def test_fp32_perturbation_matches_fp64_oracle_3d(n, ny, nz):
+    cfg, U0, meta = W.strat3d(n=n, nz=nz, ny=ny, xi=30.0)
     bg = meta["bg"]
     U1 = (U0 - bg[:, :, None, None]).astype(np.float32)
     Ustart = bg[:, :, None, None] + U1.astype(np.float64)
@@ -215,7 +218,8 @@ def test_uniform_state_bitwise_3d():
 
 
 @pytest.mark.parametrize("n,shift", [([100, 14, 12], (5, 3, 37)), ([256, 9, 6], (2, 1, 0)),
-                                     ([64, 13, 5], (1, 5, 3)), ([192, 7, 5], (3, 2, 70))])
+                                     ([64, 13, 5], (1, 5, 3)), ([192, 7, 5], (3, 2, 70)),
+                                     ([320, 5, 4], (1, 2, 131))])
 def test_translation_invariance_bitwise(n, shift):
     """A periodic shift that is not a multiple of any tile or wave moves the
     result bit for bit (tile seams and halos compute the same numbers).  The
