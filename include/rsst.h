@@ -71,10 +71,10 @@ typedef struct rsst_config {
   int n[3];          /* cells per axis (>= 4 on the used axes); axes >= ndim
                         must be 1.  Supported (else RSST_E_UNSUPPORTED): a
                         workgroup holds whole x rows, so n[0] <= 1024 in 1D
-                        and 2D and n[0] <= 512 in 3D; kernels address a state
-                        with 32-bit byte offsets, so nvar * ncell * (8 FP64,
-                        4 FP32_PERT) < 2^31, e.g. 3D FP64 up to 53.6 M cells
-                        (256 x 256 x 819)                                     */
+                        and 2D and n[0] <= 512 in 3D; a 1D or 2D state is
+                        below 2 GiB (32-bit byte offsets); a 3D state may be
+                        of any size, with each x-y plane of one variable
+                        below 2 GiB.                                          */
   double dx[3];      /* cell widths (> 0) of the used axes                    */
   double gamma;      /* ratio of specific heats, > 1                          */
   double xi;         /* reduction rate of the sound speed, >= 1 (App. A.2)    */

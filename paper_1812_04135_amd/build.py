@@ -14,8 +14,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "librsst.so")
 SOURCES = ["csrc/rsst_kernels.hip", "csrc/rsst_batch.hip", "csrc/rsst_adjoint.hip", "csrc/rsst_api.hip"]
-# the stage kernels, one object per dimension and storage type
-STAGE_UNITS = [(nd, st) for nd in (3, 2, 1) for st in ("double", "float")]
+# the stage kernels, one object per dimension, storage type and addressing
+# (big: 3D states of 2 GiB or more)
+STAGE_UNITS = [(nd, st, 0) for nd in (3, 2, 1) for st in ("double", "float")] + \
+              [(3, st, 1) for st in ("double", "float")]
 
 # -packed-fp32-ops off: no packed FP32 instructions anywhere in the library
 HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -31,10 +33,11 @@ def build(verbose: bool = False) -> str:
     inc = ["-I" + os.path.join(ROOT, "include"), "-I" + os.path.join(HERE, "csrc")]
     compile_flags = [f for f in HIPFLAGS if f != "-shared"]
     objs, cmds = [], []
-    for nd, st in STAGE_UNITS:
-        obj = os.path.join(objdir, f"rsst_stage_{nd}d_{st}.o")
+    for nd, st, big in STAGE_UNITS:
+        obj = os.path.join(objdir, f"rsst_stage_{nd}d_{st}{'_big' if big else ''}.o")
         objs.append(obj)
-        cmds.append(["hipcc"] + compile_flags + inc + [f"-DRSST_INST_NDIM={nd}", f"-DRSST_INST_ST={st}", "-c",
+        cmds.append(["hipcc"] + compile_flags + inc + [f"-DRSST_INST_NDIM={nd}", f"-DRSST_INST_ST={st}",
+                                                        f"-DRSST_INST_BIG={big}", "-c",
                                                         os.path.join(HERE, "csrc/rsst_stage_inst.hip"), "-o", obj])
     for src in SOURCES:
         obj = os.path.join(objdir, os.path.basename(src).replace(".hip", ".o"))

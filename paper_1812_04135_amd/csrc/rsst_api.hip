@@ -85,11 +85,13 @@ static int validate(const rsst_config* c) {
     if (c->prec != RSST_FP64 || c->cmax > 0.0 || (c->flags & RSST_WITH_ADJOINT))
       return RSST_E_UNSUPPORTED;
   }
-  // fields are addressed with 32-bit byte offsets
+  // 1D and 2D states are addressed with 32-bit byte offsets; 3D states of
+  // 2 GiB or more one x-y plane at a time, with 32-bit offsets inside it
   {
+    const int sz = c->prec == RSST_FP32_PERT ? 4 : 8;
     const long long cells = (long long)c->n[0] * c->n[1] * c->n[2];
-    const long long bytes = cells * (c->ndim + 2) * (c->prec == RSST_FP32_PERT ? 4 : 8);
-    if (bytes >= (1ll << 31)) return RSST_E_UNSUPPORTED;
+    if (c->ndim < 3 && cells * (c->ndim + 2) * sz >= (1ll << 31)) return RSST_E_UNSUPPORTED;
+    if (c->ndim == 3 && (long long)c->n[0] * c->n[1] * sz >= (1ll << 31)) return RSST_E_UNSUPPORTED;
   }
   // supported launch shapes: whole x rows in one workgroup
   if (c->ndim == 1 && c->n[0] > 1024) return RSST_E_UNSUPPORTED;
@@ -176,6 +178,7 @@ int rsst_init(const rsst_config* cfg, void* stream, rsst_handle* out) {
   if (hipMalloc(&h->u1, ubytes) != hipSuccess) { delete h; return RSST_E_NOMEM; }
   const size_t nscal = rsstk::kNumScalars;
   a.nblk = a.geo.ntile_s * a.geo.nchunk;
+  a.big = (cfg->ndim == 3 && (long long)h->nv * h->ncell * (long long)h->elem >= (1ll << 31)) ? 1 : 0;
   h->scal = h->blkmax = h->part = h->diag_out = nullptr;
   if (hipMalloc((void**)&h->scal, nscal * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&h->blkmax, (size_t)a.nblk * sizeof(double)) != hipSuccess ||

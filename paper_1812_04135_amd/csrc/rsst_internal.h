@@ -40,6 +40,7 @@ struct StageArgs {
   double dt_fixed;   // > 0: use it, else scal[kDtCur]
   double cfl_h;      // cfl * h, h from the dt rule
   double t_end;      // > 0: cut dt at t_end
+  int big;           // 3D state of 2 GiB or more (64-bit plane bases)
   double* scal;      // device scalars
   double* blkmax;    // [nblk] largest c_tot of the current state per stage-2 workgroup
   int nblk;          // stage-kernel workgroups (ntile_s * nchunk)
@@ -56,8 +57,10 @@ struct StageArgs {
 Geometry plan_geometry(int ndim, const int n[3]);
 
 hipError_t launch_stage(const StageArgs& a, int stage, hipStream_t s);
-// One instantiation per (NDIM, ST) lives in its own object (rsst_stage_inst.hip).
-template <int NDIM, typename ST>
+// One instantiation per (NDIM, ST, BIG) lives in its own object
+// (rsst_stage_inst.hip); BIG: a 3D state of 2 GiB or more, addressed one
+// plane at a time with 64-bit bases.
+template <int NDIM, typename ST, bool BIG>
 hipError_t launch_stage_n(const StageArgs& a, int stage, hipStream_t s);
 // nsteps whole steps of a 1D grid (one workgroup) in one launch; a1 and a2
 // are the stage-1 and stage-2 arguments of rsst_stage.

@@ -220,9 +220,9 @@ Geometry plan_geometry(int ndim, const int n[3]) {
 template <typename ST>
 static hipError_t launch_stage_p(const StageArgs& a, int stage, hipStream_t s) {
   switch (a.geo.ndim) {
-    case 1: return launch_stage_n<1, ST>(a, stage, s);
-    case 2: return launch_stage_n<2, ST>(a, stage, s);
-    default: return launch_stage_n<3, ST>(a, stage, s);
+    case 1: return launch_stage_n<1, ST, false>(a, stage, s);
+    case 2: return launch_stage_n<2, ST, false>(a, stage, s);
+    default: return a.big ? launch_stage_n<3, ST, true>(a, stage, s) : launch_stage_n<3, ST, false>(a, stage, s);
   }
 }
 

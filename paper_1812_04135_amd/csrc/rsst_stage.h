@@ -3,6 +3,8 @@
 // The decomposition is described in rsst_kernels.hip.
 #pragma once
 
+#include <type_traits>
+
 #include "rsst_device.h"
 #include "rsst_internal.h"
 
@@ -40,14 +42,53 @@ __device__ __forceinline__ double hydro_lever(int q, int n, int bc_lo, int bc_hi
   return 0.0;
 }
 
-// Raw buffer access to a field: one resource per field (bounds-checked by
-// the hardware against the field's byte size), a workgroup-uniform byte
-// offset in an SGPR (plane and variable) and a loop-invariant per-thread
-// byte offset in a VGPR (the column), so no vector address arithmetic.
+// Raw buffer access: a resource built in scalar registers (base and range,
+// see Field32 and Field64) and a loop-invariant per-thread byte offset in a
+// VGPR (the column), so no vector address arithmetic.
 typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t field_rsrc(const void* p, long long bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+// A state: nvar arrays of ncell values, read and written one plane (3D: an
+// x-y plane; 2D: a row) and one variable at a time.  Two addressings, the
+// same accesses:
+//  Field32 (states below 2 GiB): one resource for the whole state and a
+//    workgroup-uniform 32-bit offset (plane and variable) in an SGPR;
+//  Field64 (any size): per access a resource whose 64-bit base is that plane
+//    of that variable and whose range is the plane, so no offset the hardware
+//    adds exceeds a plane.  Its scalar address arithmetic costs the 3D kernels
+//    about 2%, so the library uses it only for states of 2 GiB or more.
+struct Field32 {
+  __amdgpu_buffer_rsrc_t r;
+  int vbytes;  // bytes of one variable's array
+  int pbytes;  // bytes of one plane
+  __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(int, int) const { return r; }
+  __device__ __forceinline__ int soff(int v, int k) const { return k * pbytes + v * vbytes; }
+};
+
+struct Field64 {
+  const char* p;     // variable 0, plane 0
+  long long vbytes;  // bytes of one variable's array
+  int pbytes;        // bytes of one plane
+  __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(int v, int k) const {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(p + v * vbytes + (long long)k * pbytes), (short)0,
+                                             pbytes, 0x00020000);
+  }
+  __device__ __forceinline__ int soff(int, int) const { return 0; }
+};
+
+template <bool BIG>
+using FieldT = typename std::conditional<BIG, Field64, Field32>::type;
+
+template <bool BIG>
+__device__ __forceinline__ FieldT<BIG> make_field(const void* p, long long ncell, int nv, int sz, int pbytes) {
+  if constexpr (BIG) {
+    return Field64{(const char*)p, ncell * sz, pbytes};
+  } else {
+    return Field32{field_rsrc(p, (long long)nv * ncell * sz), (int)(ncell * sz), pbytes};
+  }
 }
 
 template <typename ST>
@@ -97,12 +138,11 @@ __device__ __forceinline__ ST buf_load_raw(__amdgpu_buffer_rsrc_t r, int voff, i
   }
 }
 
-template <int NDIM, typename ST, int AUX = 0>
-__device__ __forceinline__ void load_cell_raw(const StageArgs& A, __amdgpu_buffer_rsrc_t r, int soff, int voff,
-                                              ST (&raw)[NDIM + 2]) {
-  const int vstride = (int)(A.ncell * (long long)sizeof(ST));
+// The stored values of the cell at column byte offset voff of plane k.
+template <int NDIM, typename ST, int AUX = 0, typename F>
+__device__ __forceinline__ void load_cell_raw(const F& f, int k, int voff, ST (&raw)[NDIM + 2]) {
 #pragma unroll
-  for (int v = 0; v < NDIM + 2; ++v) raw[v] = buf_load_raw<ST, AUX>(r, voff, soff + v * vstride);
+  for (int v = 0; v < NDIM + 2; ++v) raw[v] = buf_load_raw<ST, AUX>(f.rsrc(v, k), voff, f.soff(v, k));
 }
 
 // FP64 cell state from its stored values: widening and background (FP32
@@ -160,15 +200,14 @@ __device__ __forceinline__ void load_bg(__amdgpu_buffer_rsrc_t r, int nbg, int i
   }
 }
 
-// Cell state at byte offsets (soff: workgroup-uniform plane offset, voff:
-// the thread's column) as FP64; `negv` >= 0 names a momentum component to
-// negate (mirror ghost); b: background index (FP32 perturbation form).
-template <int NDIM, typename ST>
-__device__ __forceinline__ void load_cell(const StageArgs& A, __amdgpu_buffer_rsrc_t r, int soff,
-                                          int voff, int negv, int b, double (&u)[NDIM + 2],
-                                          double lever = 0.0) {
+// Cell state at plane k (workgroup-uniform) and column byte offset voff
+// (the thread's) as FP64; `negv` >= 0 names a momentum component to negate
+// (mirror ghost); b: background index (FP32 perturbation form).
+template <int NDIM, typename ST, typename F>
+__device__ __forceinline__ void load_cell(const StageArgs& A, const F& f, int k, int voff, int negv, int b,
+                                          double (&u)[NDIM + 2], double lever = 0.0) {
   ST raw[NDIM + 2];
-  load_cell_raw<NDIM, ST>(A, r, soff, voff, raw);
+  load_cell_raw<NDIM, ST>(f, k, voff, raw);
   finish_cell<NDIM, ST>(A, raw, negv, b, u, lever);
 }
 
@@ -257,7 +296,7 @@ __host__ __device__ constexpr int tile_rows(int nwx) {
 // NWXC = 0: 1D/2D, nwx and the number of row groups from the geometry.
 // Every row of the workgroup runs the same number of march iterations
 // (G.km), so rows of different chunks share the workgroup's barriers.
-template <int NDIM, int STAGE, typename ST, int FORMX, int NWXC>
+template <int NDIM, int STAGE, typename ST, int FORMX, int NWXC, bool BIG = false>
 __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, int tile_s,
                                              int chunk_base, double dt, unsigned& bad) {
   constexpr int FORM = FORMX & 7;     // correction form
@@ -322,7 +361,6 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
   constexpr int SZ = (int)sizeof(ST);
   const int plane = G.nx * G.ns * SZ;              // bytes per march plane
   const int col = (j * G.nx + i) * SZ;             // this thread's column (bytes)
-  const long long fbytes = (long long)NV * A.ncell * SZ;
   const int bgi_xy = (sizeof(ST) == 4 && !A.bg_uniform) ? bg_index<NDIM>(A, i, j, 0) : 0;
   const bool bg_on_m = (sizeof(ST) == 4) && (A.bg_axis == am) && HM;
   auto bgk = [&](int kk) { return bg_on_m ? kk : bgi_xy; };
@@ -343,12 +381,11 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
   const Consts K{A.gamma, A.gm1, A.inv_gm1, A.inv_xi, A.f, A.inv_cmax2, A.vdw_a, A.vdw_b};
   const double g[3] = {A.g[0], A.g[1], A.g[2]};
   const double hx = 0.5 * A.inv_dx[0], hy = 0.5 * A.inv_dx[1], hz = 0.5 * A.inv_dx[DM];
-  const __amdgpu_buffer_rsrc_t uin = field_rsrc(A.uin, fbytes);
-  const __amdgpu_buffer_rsrc_t unp = field_rsrc(A.un ? A.un : A.uin, fbytes);
+  const FieldT<BIG> uin = make_field<BIG>(A.uin, A.ncell, NV, SZ, plane);
+  const FieldT<BIG> unp = make_field<BIG>(A.un ? A.un : A.uin, A.ncell, NV, SZ, plane);
   // stage 2 writes the new state in place over the step-start state (the
-  // callers pass uout == un), so one resource serves both
-  const __amdgpu_buffer_rsrc_t uout = STAGE == 2 ? unp : field_rsrc(A.uout, fbytes);
-  const int vstride = (int)(A.ncell * (long long)SZ);
+  // callers pass uout == un), so one field serves both
+  const FieldT<BIG> uout = STAGE == 2 ? unp : make_field<BIG>(A.uout, A.ncell, NV, SZ, plane);
 
   // y rows just outside the tile (3D): columns and mirror flags, once
   int clo1 = 0, clo2 = 0, chi1 = 0, chi2 = 0, nlo1 = -1, nlo2 = -1, nhi1 = -1, nhi2 = -1;
@@ -402,14 +439,14 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
     bool n;
     int kk;
     kk = map_index(k0l - 2, G.nm, rm_lo, rm_hi, n);
-    load_cell<NDIM, ST>(A, uin, kk * plane, col, n ? NDIM : -1, bgk(kk), qa,
+    load_cell<NDIM, ST>(A, uin, kk, col, n ? NDIM : -1, bgk(kk), qa,
                         HYD ? hydro_lever(k0l - 2, G.nm, rm_lo, rm_hi, A.dx[am], A.g[am]) : 0.0);
     kk = map_index(k0l - 1, G.nm, rm_lo, rm_hi, n);
-    load_cell<NDIM, ST>(A, uin, kk * plane, col, n ? NDIM : -1, bgk(kk), qb,
+    load_cell<NDIM, ST>(A, uin, kk, col, n ? NDIM : -1, bgk(kk), qb,
                         HYD ? hydro_lever(k0l - 1, G.nm, rm_lo, rm_hi, A.dx[am], A.g[am]) : 0.0);
-    load_cell<NDIM, ST>(A, uin, k0l * plane, col, -1, bgk(k0l), q0);
+    load_cell<NDIM, ST>(A, uin, k0l, col, -1, bgk(k0l), q0);
     kk = map_index(k0l + 1, G.nm, rm_lo, rm_hi, n);
-    load_cell<NDIM, ST>(A, uin, kk * plane, col, n ? NDIM : -1, bgk(kk), q1,
+    load_cell<NDIM, ST>(A, uin, kk, col, n ? NDIM : -1, bgk(kk), q1,
                         HYD ? hydro_lever(k0l + 1, G.nm, rm_lo, rm_hi, A.dx[am], A.g[am]) : 0.0);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -424,11 +461,11 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
     load_cell<NDIM, ST>(A, uin, 0, col, -1, bgi_xy, q0);
   }
   if constexpr (pre) {
-    load_cell_raw<NDIM, ST>(A, uin, k0l * plane, oc1, o1);
-    load_cell_raw<NDIM, ST>(A, uin, k0l * plane, oc2, o2);
+    load_cell_raw<NDIM, ST>(uin, k0l, oc1, o1);
+    load_cell_raw<NDIM, ST>(uin, k0l, oc2, o2);
     if constexpr (ONE) {
-      load_cell_raw<NDIM, ST>(A, uin, k0l * plane, chi1, o3);
-      load_cell_raw<NDIM, ST>(A, uin, k0l * plane, chi2, o4);
+      load_cell_raw<NDIM, ST>(uin, k0l, chi1, o3);
+      load_cell_raw<NDIM, ST>(uin, k0l, chi2, o4);
     }
   }
 
@@ -436,7 +473,6 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
     const int kraw = k0 + it;
     const bool kval = kraw < k1;
     const int k = min(kraw, G.nm - 1);  // plane used for loads and stores
-    const int koff = k * plane;
     // ---- loads for this iteration: the plane two ahead, the step-start state
     // (stored values now, finished where first used, so the loads overlap
     // this plane's work)
@@ -456,8 +492,8 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
         load_bg<NV>(bgr, A.nbg, q2k, bgB);
       }
     }
-    if constexpr (HM) load_cell_raw<NDIM, ST>(A, uin, q2k * plane, col, q2r);
-    if constexpr (STAGE == 2) load_cell_raw<NDIM, ST, HS ? RSST_UN_AUX : 0>(A, unp, koff, col, unr);
+    if constexpr (HM) load_cell_raw<NDIM, ST>(uin, q2k, col, q2r);
+    if constexpr (STAGE == 2) load_cell_raw<NDIM, ST, HS ? RSST_UN_AUX : 0>(unp, k, col, unr);
 
     // ---- P1: publish this plane's cell state
     if constexpr (HS) {
@@ -598,11 +634,11 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
     }
     if constexpr (pre) {  // the outside rows of the next plane
       const int kn = min(kraw + 1, G.nm - 1);
-      load_cell_raw<NDIM, ST>(A, uin, kn * plane, oc1, o1);
-      load_cell_raw<NDIM, ST>(A, uin, kn * plane, oc2, o2);
+      load_cell_raw<NDIM, ST>(uin, kn, oc1, o1);
+      load_cell_raw<NDIM, ST>(uin, kn, oc2, o2);
       if constexpr (ONE) {
-        load_cell_raw<NDIM, ST>(A, uin, kn * plane, chi1, o3);
-        load_cell_raw<NDIM, ST>(A, uin, kn * plane, chi2, o4);
+        load_cell_raw<NDIM, ST>(uin, kn, chi1, o3);
+        load_cell_raw<NDIM, ST>(uin, kn, chi2, o4);
       }
     }
     __syncthreads();  // B2
@@ -706,7 +742,7 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
         double bgv = 0.0;
         if constexpr (F32) bgv = bgA[v];  // plane k (or this cell's invariant values)
         const ST st = (ST)(y - bgv);
-        buf_store<ST, HS ? RSST_ST_AUX : 0>(uout, col, koff + v * vstride, st);
+        buf_store<ST, HS ? RSST_ST_AUX : 0>(uout.rsrc(v, k), col, uout.soff(v, k), st);
         out[v] = (double)st + bgv;
       }
       if constexpr (STAGE == 2) cmax = fmax(cmax, cell_ctot<NDIM, EXT>(out, K));

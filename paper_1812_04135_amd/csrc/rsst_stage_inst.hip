@@ -1,7 +1,8 @@
 // Stage kernels of one dimension and storage type, instantiated for every
 // form (with and without xi from the sound speed), row width and stage.
-// Compiled once per (RSST_INST_NDIM, RSST_INST_ST) so the library builds in
-// parallel objects.
+// Compiled once per (RSST_INST_NDIM, RSST_INST_ST, RSST_INST_BIG) so the
+// library builds in parallel objects; RSST_INST_BIG = 1 builds the 3D
+// kernels that address states of 2 GiB or more (Field64).
 #include "rsst_stage.h"
 
 #pragma clang fp contract(off)
@@ -11,6 +12,9 @@
 #endif
 #ifndef RSST_INST_ST
 #error "RSST_INST_ST (double or float) must be defined"
+#endif
+#ifndef RSST_INST_BIG
+#define RSST_INST_BIG 0
 #endif
 
 namespace rsstk {
@@ -24,7 +28,9 @@ namespace rsstk {
 #define RSST_WPE3 1
 #endif
 
-template <int NDIM, int STAGE, typename ST, int FORM, int NWXC>
+constexpr bool kBig = RSST_INST_BIG != 0;
+
+template <int NDIM, int STAGE, typename ST, int FORM, int NWXC, bool BIG>
 __global__ void __launch_bounds__(NDIM == 3 ? RSST_LB3 : 1024)
     __attribute__((amdgpu_waves_per_eu(NDIM == 3 ? RSST_WPE3 : 1))) stage_kernel(const StageArgs A) {
   extern __shared__ double lds[];
@@ -45,7 +51,7 @@ __global__ void __launch_bounds__(NDIM == 3 ? RSST_LB3 : 1024)
     }
   }
   unsigned bad = 0;
-  const double cmax = stage_body<NDIM, STAGE, ST, FORM, NWXC>(A, lds, tile_s, chunk_base, dt, bad);
+  const double cmax = stage_body<NDIM, STAGE, ST, FORM, NWXC, BIG>(A, lds, tile_s, chunk_base, dt, bad);
   if (bad) atomicOr((unsigned*)(A.scal + kFlags), bad);
   if constexpr (STAGE == 2) cfl_epilogue(A, lds + C.red, cmax, dt);
 }
@@ -54,7 +60,7 @@ template <int NDIM, int STAGE, typename ST, int FORM, int NWXC>
 static hipError_t launch_stage_k(const StageArgs& a, hipStream_t s) {
   const Geometry& G = a.geo;
   const dim3 grid((unsigned)(G.ntile_s * G.nchunk)), block((unsigned)G.threads);
-  auto kern = stage_kernel<NDIM, STAGE, ST, FORM, NWXC>;
+  auto kern = stage_kernel<NDIM, STAGE, ST, FORM, NWXC, kBig>;
   // raise the kernel's LDS limit only when a larger tile needs it, so launches
   // of a known shape (e.g. under HIP graph capture) make no attribute call
   static int lds_set[64] = {0};
@@ -123,14 +129,15 @@ static hipError_t launch_stage_f(const StageArgs& a, hipStream_t s) {
   }
 }
 
-template <int NDIM, typename ST>
+template <int NDIM, typename ST, bool BIG>
 hipError_t launch_stage_n(const StageArgs& a, int stage, hipStream_t s) {
+  static_assert(BIG == kBig, "one addressing per object");
   return stage == 1 ? launch_stage_f<NDIM, 1, ST>(a, s) : launch_stage_f<NDIM, 2, ST>(a, s);
 }
 
-template hipError_t launch_stage_n<RSST_INST_NDIM, RSST_INST_ST>(const StageArgs&, int, hipStream_t);
+template hipError_t launch_stage_n<RSST_INST_NDIM, RSST_INST_ST, kBig>(const StageArgs&, int, hipStream_t);
 
-#if RSST_INST_NDIM == 1
+#if RSST_INST_NDIM == 1 && !RSST_INST_BIG
 // nsteps whole steps of a 1D grid in one launch.  A 1D grid is one workgroup
 // (a row of at most 16 waves), so both stages and the CFL maximum of every
 // step run in that workgroup with barriers in between: the stage bodies are

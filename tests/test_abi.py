@@ -89,11 +89,13 @@ def test_unsupported_shape_reported():
     c = R.make_config(cfg)
     h = ctypes.c_void_p()
     assert R.lib().rsst_init(ctypes.byref(c), None, ctypes.byref(h)) == -4
-    # rows wider than one workgroup, and fields past 2 GiB (32-bit byte
-    # offsets), are reported on the host; the largest supported ones pass
-    # validation up to the device allocation (not attempted here)
-    for n, ok in (([1025], False), ([1025, 8], False), ([256, 256, 819], True), ([256, 256, 820], False),
-                  ([512, 8, 8], True), ([513, 8, 8], False)):
+    # rows wider than one workgroup, 3D x-y planes past 2 GiB (32-bit byte
+    # offsets inside a plane) and 1D/2D states past 2 GiB are reported on the
+    # host; the largest supported ones pass validation up to the device
+    # allocation (not attempted here), 3D states past 2 GiB included
+    for n, ok in (([1025], False), ([1025, 8], False), ([256, 256, 8192], True), ([512, 8, 8], True),
+                  ([513, 8, 8], False), ([512, 524287, 4], True), ([512, 524288, 4], False),
+                  ([1024, 65535], True), ([1024, 65536], False)):
         cfg = W.base_cfg(len(n), n)
         c = R.make_config(cfg)
         code = R.lib().rsst_init(ctypes.byref(c), None, ctypes.byref(h))

@@ -1,0 +1,52 @@
+"""A 3D state past 4 GiB: 256 x 256 x 2048 cells in FP64 (5.4 GB; variable 4
+starts 4.3 GB into the array), built as 256 copies along z of one random
+periodic 256 x 256 x 8 block.  The step is translation invariant bit for bit,
+so after two steps every copy equals the block's own two steps, which in turn
+match the oracle (1e-12 of the natural scales).  A kernel that wrapped a
+32-bit offset would read or write the wrong plane of the wrong variable in
+the upper copies."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def test_state_past_4_gib():
+    import paper_1812_04135_amd as R
+    assert torch.cuda.is_available()
+    R.lib()
+    cfg, Ub = W.random_state(3, [256, 256, 8], seed_k=950, xi=4.0, mach=0.3)
+    print("[case] large 256x256x2048 FP64 from a 256x256x8 block", flush=True)
+    # the block on the GPU against the oracle
+    U = torch.from_numpy(Ub.copy()).cuda()
+    s = R.Solver(cfg)
+    s.steps(U, 2)
+    Ug = U.cpu().numpy()
+    assert s.poll() == 0
+    s.close()
+    Uo, _, _ = oracle.run(cfg, Ub, 2)
+    scale = [np.abs(Uo[0]).max()] * 4 + [np.abs(Uo[4]).max()]
+    err = max(float(np.abs(Ug[v] - Uo[v]).max() / scale[v]) for v in range(5))
+    print(f"[parity] block err/scale {err:.2e}", flush=True)
+    assert err <= 1e-12
+    # the tiled state
+    reps = 256
+    big = dict(cfg, n=[256, 256, 8 * reps])
+    Ut = torch.from_numpy(Ub).cuda().repeat(1, reps, 1, 1).contiguous()
+    assert Ut.numel() * 8 > 4 * 2 ** 30
+    s = R.Solver(big)
+    s.steps(Ut, 2)
+    torch.cuda.synchronize()
+    assert s.poll() == 0
+    s.close()
+    ref = torch.from_numpy(Ug).cuda()
+    copies = Ut.view(5, reps, 8, 256, 256)
+    same = (copies == ref[:, None]).flatten(1).all(dim=1)
+    print(f"[large] copies equal to the block per variable: {same.tolist()}", flush=True)
+    assert bool(same.all())
+    del Ut, copies
+    torch.cuda.empty_cache()
