@@ -50,3 +50,47 @@ def test_state_past_4_gib():
     assert bool(same.all())
     del Ut, copies
     torch.cuda.empty_cache()
+
+
+def test_fp32_perturbation_state_past_4_gib():
+    """The same check in the FP32 perturbation form: 256 x 256 x 4096 cells
+    of FP32 perturbations (5.4 GB) about a uniform FP64 background, 512
+    copies of one 8-plane block; the block itself against the FP64 oracle
+    at the FP32 bar (1e-5 of the perturbation)."""
+    import paper_1812_04135_amd as R
+    assert torch.cuda.is_available()
+    R.lib()
+    cfg, Ub = W.random_state(3, [256, 256, 8], seed_k=951, xi=4.0, mach=0.3)
+    bg = np.ascontiguousarray(Ub.reshape(5, -1).mean(axis=1)[:, None])  # [nv][1]
+    U1 = (Ub - bg[:, :, None, None]).astype(np.float32)
+    Ustart = bg[:, :, None, None] + U1.astype(np.float64)
+    print("[case] large FP32 256x256x4096 from a 256x256x8 block", flush=True)
+    bgt = torch.from_numpy(bg).cuda()
+    U = torch.from_numpy(U1.copy()).cuda()
+    s = R.Solver(cfg, prec="fp32_pert", bg=bgt, bg_axis=-1)
+    s.steps(U, 2)
+    Ug = U.cpu().numpy()
+    assert s.poll() == 0
+    s.close()
+    Uo, _, _ = oracle.run(cfg, Ustart, 2)
+    pert = Uo - bg[:, :, None, None]
+    sc = [np.abs(pert[v]).max() for v in range(5)]
+    sc = [sc[0]] + [max(sc[1:4])] * 3 + [sc[4]]
+    err = max(float(np.abs(Ug[v].astype(np.float64) - pert[v]).max() / sc[v]) for v in range(5))
+    print(f"[parity] FP32 block err/|pert| {err:.2e}", flush=True)
+    assert err <= 1e-5
+    reps = 512
+    big = dict(cfg, n=[256, 256, 8 * reps])
+    Ut = torch.from_numpy(U1).cuda().repeat(1, reps, 1, 1).contiguous()
+    assert Ut.numel() * 4 > 4 * 2 ** 30
+    s = R.Solver(big, prec="fp32_pert", bg=bgt, bg_axis=-1)
+    s.steps(Ut, 2)
+    torch.cuda.synchronize()
+    assert s.poll() == 0
+    s.close()
+    ref = torch.from_numpy(Ug).cuda()
+    same = (Ut.view(5, reps, 8, 256, 256) == ref[:, None]).flatten(1).all(dim=1)
+    print(f"[large] FP32 copies equal to the block per variable: {same.tolist()}", flush=True)
+    assert bool(same.all())
+    del Ut
+    torch.cuda.empty_cache()
