@@ -524,20 +524,27 @@ def main():
         sol.diag(U)
     sec["diag_strat3d_256_ms"] = round((time.perf_counter() - td) / 20 * 1e3, 4)
 
-    # 1D wave, 256 cells, xi = 10, the whole run to t_end (2 reduced crossings)
+    # 1D wave, 256 cells, xi = 10, the whole run to t_end (2 reduced crossings):
+    # one untimed run (first launch of the kernel), then three timed ones
     cfg1, U1w, meta1 = W.wave1d(xi=10.0)
-    Uw = torch.from_numpy(U1w).to(dev)
-    s1 = R.Solver(cfg1, t_end=meta1["t_end"])
-    torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record(stream)
-    s1.steps(Uw, 1300)
-    b.record(stream)
-    torch.cuda.synchronize()
-    t1, _ = s1.time()
-    s1.close()
+    rates = []
+    for rep in range(4):
+        Uw = torch.from_numpy(U1w).to(dev)
+        s1 = R.Solver(cfg1, t_end=meta1["t_end"])
+        s1.prime(Uw)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        s1.steps(Uw, 1300)
+        b.record(stream)
+        torch.cuda.synchronize()
+        t1, _ = s1.time()
+        s1.close()
+        if rep > 0:
+            rates.append(round(1300 / (a.elapsed_time(b) * 1e-3), 1))
     sec["wave1d_256_xi10"] = {"steps": 1300, "t_reached": t1, "t_end": meta1["t_end"],
-                              "steps_per_s": round(1300 / (a.elapsed_time(b) * 1e-3), 1)}
+                              "steps_per_s": float(np.median(rates)), "steps_per_s_all": rates,
+                              "timing": "median of 3 runs after one untimed run"}
     # batched sweep: 512 stratified 2D boxes (N in 64..256, contrast 3..100,
     # xi 1..50), 200 steps with per-box CFL dt in one persistent launch
     # replayed from a HIP graph; FP32 perturbation (the workload) and FP64

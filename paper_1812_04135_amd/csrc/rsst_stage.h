@@ -296,9 +296,20 @@ __host__ __device__ constexpr int tile_rows(int nwx) {
 // NWXC = 0: 1D/2D, nwx and the number of row groups from the geometry.
 // Every row of the workgroup runs the same number of march iterations
 // (G.km), so rows of different chunks share the workgroup's barriers.
-template <int NDIM, int STAGE, typename ST, int FORMX, int NWXC, bool BIG = false>
+// A 1D cell kept in registers across stages (steps1d_kernel): the stage
+// input, the step-start state, the output, and the output's stored value
+// (widened).  in and un hold exactly what loading the stored values would
+// give, so the results are those of the stored path.
+template <int NV>
+struct RegCell {
+  double in[NV], un[NV], out[NV], st[NV];
+};
+
+template <int NDIM, int STAGE, typename ST, int FORMX, int NWXC, bool BIG = false, bool REG = false>
 __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, int tile_s,
-                                             int chunk_base, double dt, unsigned& bad) {
+                                             int chunk_base, double dt, unsigned& bad,
+                                             RegCell<NDIM + 2>* rc = nullptr) {
+  static_assert(!REG || NDIM == 1, "register-resident cells: 1D only");
   constexpr int FORM = FORMX & 7;     // correction form
   constexpr int EXT = FORMX & (kExtCmax | kExtVdw);  // xi from eq. cx; van der Waals gas
   constexpr bool HYD = (FORMX & kExtHydro) != 0;     // hydrostatic walls (y, march axis)
@@ -457,6 +468,9 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
     make_face<NDIM, DM, EXT>(qb, ha, true, K, fl);
     make_face<NDIM, DM, EXT>(q0, sm0, false, K, fr);
     flux2<NDIM, DM>(fl, fr, Fm_lo);
+  } else if constexpr (REG) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) q0[v] = rc->in[v];
   } else {
     load_cell<NDIM, ST>(A, uin, 0, col, -1, bgi_xy, q0);
   }
@@ -493,7 +507,7 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
       }
     }
     if constexpr (HM) load_cell_raw<NDIM, ST>(uin, q2k, col, q2r);
-    if constexpr (STAGE == 2) load_cell_raw<NDIM, ST, HS ? RSST_UN_AUX : 0>(unp, k, col, unr);
+    if constexpr (STAGE == 2 && !REG) load_cell_raw<NDIM, ST, HS ? RSST_UN_AUX : 0>(unp, k, col, unr);
 
     // ---- P1: publish this plane's cell state
     if constexpr (HS) {
@@ -728,7 +742,10 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
     double R[NV];
     const unsigned b = rsst_rate<NDIM, FORM, EXT>(q0, Dl, K, g, R);
     double un[NV];
-    if constexpr (STAGE == 2) {
+    if constexpr (STAGE == 2 && REG) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) un[v] = rc->un[v];
+    } else if constexpr (STAGE == 2) {
       if constexpr (F32) finish_cell_bgv<NDIM, ST>(unr, -1, bgA, un);
       else finish_cell<NDIM, ST>(A, unr, -1, bgk(k), un);
     }
@@ -742,8 +759,13 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
         double bgv = 0.0;
         if constexpr (F32) bgv = bgA[v];  // plane k (or this cell's invariant values)
         const ST st = (ST)(y - bgv);
-        buf_store<ST, HS ? RSST_ST_AUX : 0>(uout.rsrc(v, k), col, uout.soff(v, k), st);
+        if constexpr (REG) {
+          rc->st[v] = (double)st;
+        } else {
+          buf_store<ST, HS ? RSST_ST_AUX : 0>(uout.rsrc(v, k), col, uout.soff(v, k), st);
+        }
         out[v] = (double)st + bgv;
+        if constexpr (REG) rc->out[v] = out[v];
       }
       if constexpr (STAGE == 2) cmax = fmax(cmax, cell_ctot<NDIM, EXT>(out, K));
     }

@@ -140,18 +140,21 @@ template hipError_t launch_stage_n<RSST_INST_NDIM, RSST_INST_ST, kBig>(const Sta
 #if RSST_INST_NDIM == 1 && !RSST_INST_BIG
 // nsteps whole steps of a 1D grid in one launch.  A 1D grid is one workgroup
 // (a row of at most 16 waves), so both stages and the CFL maximum of every
-// step run in that workgroup with barriers in between: the stage bodies are
-// those of stage_kernel, each step's dt is formed from the previous step's
-// maximum as stage 1 forms it from the stored maxima, and t and dt stay in
-// registers (t and the last maximum are stored at the end), so the state, t
-// and the next dt after each step are bitwise those of the per-stage
-// launches.  Each lane
-// reads back only its own cell between the stages (neighbours come by DPP and
-// LDS), and the workgroup barrier orders those stores and loads.  With a CFL
-// step and an end time, the steps after t reaches t_end (dt = 0, which would
-// leave U unchanged) are skipped.  a1: stage 1 (U -> U1), a2: stage 2.
+// step run in that workgroup with barriers in between, and each lane keeps
+// its own cell in registers from the first load to the last store: the
+// stage bodies are those of stage_kernel in their register-resident form
+// (stage input, step-start state and output in registers, each equal to
+// what storing and reloading would give; neighbours come by DPP and LDS as
+// always), each step's dt is formed from the previous step's maximum as
+// stage 1 forms it from the stored maxima, and t and dt stay in registers.
+// So the state, t and the next dt after each step are bitwise those of the
+// per-stage launches.  U is written once, at the end (and the stage buffer
+// not at all).  With a CFL step and an end time, the steps after t reaches
+// t_end (dt = 0, which would leave U unchanged) are skipped.  a1: stage 1
+// (U -> U1), a2: stage 2.
 template <typename ST, int FORM>
 __global__ void __launch_bounds__(1024) steps1d_kernel(const StageArgs a1, const StageArgs a2, int nsteps) {
+  constexpr int NV = 3;
   extern __shared__ double lds[];
   const Geometry& G = a1.geo;
   double* red = lds + carve(1, G.ts, G.nwx).red;
@@ -162,13 +165,36 @@ __global__ void __launch_bounds__(1024) steps1d_kernel(const StageArgs a1, const
     dt = a1.cfl_h / a1.blkmax[0];
     if (a1.t_end > 0.0) dt = fmin(dt, fmax(a1.t_end - t, 0.0));
   }
+  // this lane's cell (lanes past the row hold the last cell and store nothing)
+  const int i = min((int)threadIdx.x, G.nx - 1);
+  RegCell<NV> c;
+  {
+    ST raw[NV];
+    load_cell_raw<1, ST>(make_field<false>(a1.uin, a1.ncell, NV, (int)sizeof(ST), G.nx * (int)sizeof(ST)), 0,
+                         i * (int)sizeof(ST), raw);
+    const int b = (sizeof(ST) == 4 && !a1.bg_uniform) ? bg_index<1>(a1, i, 0, 0) : 0;
+    finish_cell<1, ST>(a1, raw, -1, b, c.in);
+  }
+  double stu[NV];  // stored values of the state after the last step
   unsigned bad = 0;
   double mlast = -1.0;
   for (int q = 0; q < nsteps; ++q) {
     if (cfl && a1.t_end > 0.0 && !(dt > 0.0)) break;
-    stage_body<1, 1, ST, FORM, 0>(a1, lds, 0, 0, dt, bad);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) c.out[v] = c.in[v];
+    stage_body<1, 1, ST, FORM, 0, false, true>(a1, lds, 0, 0, dt, bad, &c);
     __syncthreads();
-    const double cm = stage_body<1, 2, ST, FORM, 0>(a2, lds, 0, 0, dt, bad);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      c.un[v] = c.in[v];
+      c.in[v] = c.out[v];
+    }
+    const double cm = stage_body<1, 2, ST, FORM, 0, false, true>(a2, lds, 0, 0, dt, bad, &c);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      c.in[v] = c.out[v];
+      stu[v] = c.st[v];
+    }
     const double wm = wave_max(cm);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = wm;
     __syncthreads();
@@ -181,6 +207,11 @@ __global__ void __launch_bounds__(1024) steps1d_kernel(const StageArgs a1, const
       if (a1.t_end > 0.0) dt = fmin(dt, fmax(a1.t_end - t, 0.0));
     }
     __syncthreads();
+  }
+  if (mlast >= 0.0 && (int)threadIdx.x < G.nx) {
+    ST* u = (ST*)a2.uout;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) u[v * a2.ncell + i] = (ST)stu[v];
   }
   if (bad) atomicOr((unsigned*)(a1.scal + kFlags), bad);
   if (threadIdx.x == 0) {
