@@ -40,7 +40,6 @@ struct StageArgs {
   double dt_fixed;   // > 0: use it, else scal[kDtCur]
   double cfl_h;      // cfl * h, h from the dt rule
   double t_end;      // > 0: cut dt at t_end
-  int big;           // 3D state of 2 GiB or more (64-bit plane bases)
   double* scal;      // device scalars
   double* blkmax;    // [nblk] largest c_tot of the current state per stage-2 workgroup
   int nblk;          // stage-kernel workgroups (ntile_s * nchunk)
@@ -52,6 +51,7 @@ struct StageArgs {
   int nbg;
   int bg_uniform;    // background index is workgroup-uniform (-1 or the march axis)
   int prec;          // 0 FP64, 1 FP32 perturbation
+  int big;           // 3D state of 2 GiB or more (64-bit plane bases)
 };
 
 Geometry plan_geometry(int ndim, const int n[3]);
