@@ -235,6 +235,29 @@ def test_translation_invariance_bitwise(n, shift):
     assert np.array_equal(np.roll(Ua, shift=shift, axis=(1, 2, 3)), Ub)
 
 
+@pytest.mark.parametrize("ndim,n,g", [(2, [96, 40], [0.0, -0.5]), (3, [70, 9, 21], [0.0, 0.0, -0.7])])
+def test_chunk_length_changes_no_bit(ndim, n, g, monkeypatch):
+    """The march along the last axis is cut into chunks (each starting from
+    four re-read planes); the planner's chunk length (RSST_KM, read when a
+    solver is made) changes no bit of the result: 1, 2, 3, 8 planes and the
+    default, with walls and gravity along the marched axis."""
+    bc = ["periodic"] * (ndim - 1) + ["reflect"]
+    cfg, U0 = W.random_state(ndim, n, seed_k=410 + ndim, xi=3.0, bc_lo=bc, g=g, mach=0.3)
+    ref = None
+    for km in (None, "1", "2", "3", "8"):
+        if km is None:
+            monkeypatch.delenv("RSST_KM", raising=False)
+        else:
+            monkeypatch.setenv("RSST_KM", km)
+        Ug, tg, _, flags = gpu_run(cfg, U0, 4)
+        assert flags == 0
+        if ref is None:
+            ref = (Ug, tg)
+        else:
+            assert np.array_equal(Ug, ref[0]) and tg == ref[1], (km, np.abs(Ug - ref[0]).max())
+    monkeypatch.delenv("RSST_KM", raising=False)
+
+
 @pytest.mark.parametrize("form", ["dvs", "pd", "euler"])
 def test_mass_conservation_on_gpu(form):
     cfg, U0 = W.random_state(2, [96, 64], seed_k=401, xi=4.0 if form != "euler" else 1.0,
