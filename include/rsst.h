@@ -132,9 +132,10 @@ typedef struct rsst_solver* rsst_handle;
 
 /* Validates cfg on the host before touching the device (RSST_E_ARG on any
  * invalid field), then allocates the workspace (stage buffer, scalars, one
- * CFL maximum per stage-kernel workgroup) on the current device and zeroes the scalars on `stream`,
- * synchronising it before returning (so later calls may use any stream).
- * t starts at 0.  No allocation happens after this call. */
+ * CFL maximum per stage-kernel workgroup) on the current device and zeroes
+ * the scalars and maxima on `stream`, synchronising it before returning (so
+ * later calls may use any stream).  t starts at 0.  No allocation happens
+ * after this call. */
 int rsst_init(const rsst_config* cfg, void* stream, rsst_handle* out);
 
 /* Sets t = t0 and records, on the device, the maxima of c_tot over U from
@@ -153,16 +154,18 @@ int rsst_step(rsst_handle h, void* U, double dt_fixed, void* stream);
 
 /* One Runge-Kutta stage of rsst_step, for callers that schedule or time the
  * two stages separately.  stage 1: forms the step's dt (a CFL step: from the
- * recorded maxima, cut at t_end) and U1 = U + dt R(U) into the library's stage
- * buffer (U unchanged); stage 2: U <- (U + (U1 + dt R(U1))) / 2, advancing t
- * and recording the maxima of c_tot over the new U.  A stage 2 call must follow a stage 1 call on the
- * same U and dt_fixed; rsst_step(h, U, dt, s) is stage 1 then stage 2.
- * RSST_E_ARG for any other stage number. */
+ * recorded maxima, cut at t_end) and U1 = U + dt R(U) into the library's
+ * stage buffer (U unchanged); stage 2: U <- (U + (U1 + dt R(U1))) / 2,
+ * advancing t and recording the maxima of c_tot over the new U.  A stage 2
+ * call must follow a stage 1 call on the same U and dt_fixed;
+ * rsst_step(h, U, dt, s) is stage 1 then stage 2.  RSST_E_ARG for any other
+ * stage number. */
 int rsst_stage(rsst_handle h, void* U, int stage, double dt_fixed, void* stream);
 
 /* nsteps calls of rsst_step, with the same results.  A 1D grid runs as one
  * workgroup, so for ndim = 1 all nsteps steps are one launch (both stages,
- * the CFL maximum and the next dt of every step inside it); there, with a
+ * the CFL maximum and the next dt of every step inside it, U written once at
+ * the end; the stage buffer's contents are then unspecified); there, with a
  * CFL step and t_end > 0, the steps left once t reaches t_end (dt = 0, which
  * leave U unchanged) are skipped. */
 int rsst_steps(rsst_handle h, void* U, int nsteps, double dt_fixed, void* stream);
