@@ -288,14 +288,6 @@ __host__ __device__ constexpr int tile_rows(int nwx) {
   return nwx == 1 ? 8 : (nwx == 2 ? 4 : (nwx <= 4 ? RSST_TS_WIDE : 1));
 }
 
-// One stage of R over one tile (3D: TS stacked y rows of one z-chunk) or one
-// group of strips (1D/2D: row r of the workgroup marches chunk
-// chunk_base + r), returning the thread's largest c_tot of the stage-2
-// output (0 in stage 1) and or-ing non-physical flags into `bad`.
-// NWXC > 0: 3D, rows of exactly NWXC waves (compile-time LDS strides);
-// NWXC = 0: 1D/2D, nwx and the number of row groups from the geometry.
-// Every row of the workgroup runs the same number of march iterations
-// (G.km), so rows of different chunks share the workgroup's barriers.
 // A 1D cell kept in registers across stages (steps1d_kernel): the stage
 // input, the step-start state, the output, and the output's stored value
 // (widened).  in and un hold exactly what loading the stored values would
@@ -305,6 +297,16 @@ struct RegCell {
   double in[NV], un[NV], out[NV], st[NV];
 };
 
+// One stage of R over one tile (3D: TS stacked y rows of one z-chunk) or one
+// group of strips (1D/2D: row r of the workgroup marches chunk
+// chunk_base + r), returning the thread's largest c_tot of the stage-2
+// output (0 in stage 1) and or-ing non-physical flags into `bad`.
+// NWXC > 0: 3D, rows of exactly NWXC waves (compile-time LDS strides);
+// NWXC = 0: 1D/2D, nwx and the number of row groups from the geometry.
+// Every row of the workgroup runs the same number of march iterations
+// (G.km), so rows of different chunks share the workgroup's barriers.
+// BIG: Field64 addressing (3D states of 2 GiB or more).  REG (1D): the
+// thread's cell comes from and goes to *rc instead of global memory.
 template <int NDIM, int STAGE, typename ST, int FORMX, int NWXC, bool BIG = false, bool REG = false>
 __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, int tile_s,
                                              int chunk_base, double dt, unsigned& bad,
