@@ -125,7 +125,7 @@ enum rsst_eos { RSST_EOS_IDEAL = 0, RSST_EOS_VDW = 1 };
 enum rsst_flag {
   RSST_WITH_ADJOINT = 1  /* rsst_init also reserves the workspace of
                             rsst_adjoint_step (FP64 only):
-                            nvar * ncell * (3 ndim + 3) doubles               */
+                            nvar * ncell * (2 ndim + 3) doubles               */
 };
 
 typedef struct rsst_solver* rsst_handle;

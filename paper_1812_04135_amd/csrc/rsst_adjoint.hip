@@ -18,10 +18,11 @@
 // cell state (normal momentum negated), so the wall face's outer state is
 // S of the inner face state and its cotangent returns through S.
 //
-// The VJP runs as five passes, each writing only its own cells, so the
+// The VJP runs as four passes, each writing only its own cells, so the
 // result is deterministic (no atomics):
-//   A1 face   fluxes G = 2 Fhat at every face i+1/2 of every axis;
-//   A2 cell   increments Delta, reverse of correction + gravity:
+//   A2 cell   fluxes G = 2 Fhat at the cell's two faces of every axis (a
+//             face shared by two cells is formed by both, the same bits),
+//             increments Delta, reverse of correction + gravity:
 //             Delta_bar, the direct part of U_bar, the f part of xi_bar;
 //   A3 face   G_bar from Delta_bar, reverse of the LLF flux into the plus
 //             state of the left cell (Pb) and the minus state of the right
@@ -55,7 +56,6 @@ struct AdjArgs {
   const double* V;   // primal state [nv][ncell]
   const double* W;   // cotangent of R [nv][ncell]
   double* out;       // J_R^T W [nv][ncell]
-  double* F;         // [ndim][nv][ncell] face fluxes G at i+1/2
   double* Db;        // [nv][ncell]
   double* Pb;        // [ndim][nv][ncell]
   double* Mb;        // [ndim][nv][ncell]
@@ -321,31 +321,6 @@ __device__ __forceinline__ Consts adj_consts(const AdjArgs& A) {
   return Consts{A.gamma, A.gm1, A.inv_gm1, A.inv_xi, A.f};
 }
 
-template <int NDIM, int D>
-__device__ __forceinline__ void a1_axis(const AdjArgs& A, const Consts& K, long long c, const int x[3]) {
-  constexpr int NV = NDIM + 2;
-  Face<NV> L, R;
-  bool wall;
-  face_pair<NDIM, D>(A, K, c, x, L, R, wall);
-  double G[NV];
-  flux2<NDIM, D>(L, R, G);
-  double* F = A.F + (long long)D * NV * A.ncell;
-#pragma unroll
-  for (int v = 0; v < NV; ++v) F[v * A.ncell + c] = G[v];
-}
-
-template <int NDIM>
-__global__ void __launch_bounds__(kAdjThreads) adj_face_kernel(AdjArgs A) {
-  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= A.ncell) return;
-  int x[3];
-  cell_coords(A, c, x);
-  const Consts K = adj_consts<NDIM>(A);
-  a1_axis<NDIM, 0>(A, K, c, x);
-  if constexpr (NDIM >= 2) a1_axis<NDIM, 1>(A, K, c, x);
-  if constexpr (NDIM >= 3) a1_axis<NDIM, 2>(A, K, c, x);
-}
-
 __device__ __forceinline__ void block_partial(double v, double* out) {
   __shared__ double red[kAdjThreads / 64];
   const double w = wave_sum(v);
@@ -358,34 +333,41 @@ __device__ __forceinline__ void block_partial(double v, double* out) {
   }
 }
 
-// G at the face below cell c along D (the face i-1/2).
+// G at the face below cell c along D (the face i-1/2): the wall pair, or
+// the face above the neighbour below, formed as that cell forms it (so the
+// two cells sharing a face get the same bits).
 template <int NDIM, int D>
 __device__ __forceinline__ void flux_below(const AdjArgs& A, const Consts& K, long long c, const int x[3],
                                            double (&G)[NDIM + 2]) {
   constexpr int NV = NDIM + 2;
+  Face<NV> L, R;
   if (x[D] == 0 && A.refl_lo[D]) {
-    Face<NV> L, R;
     wall_lo_pair<NDIM, D>(A, K, c, x, L, R);
-    flux2<NDIM, D>(L, R, G);
   } else {
-    bool neg;
+    bool neg, wall;
     const long long q = neighbour(A, c, x, D, -1, neg);
-    const double* F = A.F + (long long)D * NV * A.ncell;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) G[v] = F[v * A.ncell + q];
+    int xq[3] = {x[0], x[1], x[2]};
+    xq[D] = x[D] == 0 ? A.n[D] - 1 : x[D] - 1;
+    face_pair<NDIM, D>(A, K, q, xq, L, R, wall);
   }
+  flux2<NDIM, D>(L, R, G);
 }
 
+// The increments of cell c along D from the fluxes of its two faces, both
+// formed here (no face pass before the cell pass).
 template <int NDIM, int D>
 __device__ __forceinline__ void a2_axis(const AdjArgs& A, const Consts& K, long long c, const int x[3],
                                         double (&Dl)[NDIM + 2]) {
   constexpr int NV = NDIM + 2;
-  double Gl[NV];
+  double Gl[NV], Gh[NV];
   flux_below<NDIM, D>(A, K, c, x, Gl);
-  const double* F = A.F + (long long)D * NV * A.ncell;
+  Face<NV> L, R;
+  bool wall;
+  face_pair<NDIM, D>(A, K, c, x, L, R, wall);
+  flux2<NDIM, D>(L, R, Gh);
   const double hd = 0.5 * A.inv_dx[D];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) Dl[v] -= (F[v * A.ncell + c] - Gl[v]) * hd;
+  for (int v = 0; v < NV; ++v) Dl[v] -= (Gh[v] - Gl[v]) * hd;
 }
 
 template <int NDIM, int FORM>
@@ -650,7 +632,6 @@ static void* cell_kernel_ptr(int form) {
 template <int NDIM>
 static hipError_t vjp_launch(AdjArgs A, int form, hipStream_t s) {
   const dim3 grid(A.nblock), block(kAdjThreads);
-  hipLaunchKernelGGL(adj_face_kernel<NDIM>, grid, block, 0, s, A);
   void* args[] = {(void*)&A};
   hipError_t e = hipLaunchKernel(cell_kernel_ptr<NDIM>(form), grid, block, args, 0, s);
   if (e != hipSuccess) return e;
@@ -663,8 +644,8 @@ static hipError_t vjp_launch(AdjArgs A, int form, hipStream_t s) {
 size_t adjoint_workspace_doubles(int ndim, long long ncell) {
   const int nv = ndim + 2;
   const long long nblock = (ncell + kAdjThreads - 1) / kAdjThreads;
-  // F, Pb, Mb: ndim fields each; Db, a/b, mu: one each; 4 partial arrays
-  return (size_t)nv * ncell * (3 * ndim + 3) + 4 * (size_t)nblock;
+  // Pb, Mb: ndim fields each; Db, a/b, mu: one each; 4 partial arrays
+  return (size_t)nv * ncell * (2 * ndim + 3) + 4 * (size_t)nblock;
 }
 
 hipError_t launch_adjoint_step(const AdjointPlan& p, const double* U, const double* U1, double* lam, double dt,
@@ -693,8 +674,7 @@ hipError_t launch_adjoint_step(const AdjointPlan& p, const double* U, const doub
   A.inv_xi = 1.0 / p.xi;
   A.f = 1.0 - 1.0 / (p.xi * p.xi);
   A.dfdxi = 2.0 / (p.xi * p.xi * p.xi);
-  A.F = w;
-  A.Pb = A.F + ndim * nf;
+  A.Pb = w;
   A.Mb = A.Pb + ndim * nf;
   A.Db = A.Mb + ndim * nf;
   double* ab = A.Db + nf;
