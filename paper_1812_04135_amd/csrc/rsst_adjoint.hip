@@ -18,7 +18,7 @@
 // cell state (normal momentum negated), so the wall face's outer state is
 // S of the inner face state and its cotangent returns through S.
 //
-// The VJP runs as four passes, each writing only its own cells, so the
+// The VJP runs as three passes, each writing only its own cells, so the
 // result is deterministic (no atomics):
 //   A2 cell   fluxes G = 2 Fhat at the cell's two faces of every axis (a
 //             face shared by two cells is formed by both, the same bits),
@@ -27,10 +27,10 @@
 //   A3 face   G_bar from Delta_bar, reverse of the LLF flux into the plus
 //             state of the left cell (Pb) and the minus state of the right
 //             cell (Mb), the alpha part of xi_bar;
-//   A4 cell   U_bar += Pb + Mb, reverse of the MC half slope h = (Pb-Mb):
-//             slope cotangents (lb, rb), stored over Pb and Mb;
-//   A5 cell   U_bar gathers -lb of the cell above and +rb of the cell below,
-//             and forms mu (first VJP) or the new lam (second VJP) from it.
+//   A4+A5 cell  U_bar += Pb + Mb, reverse of the MC half slope h = (Pb-Mb):
+//             slope cotangents (lb, rb) of the cell, and the -lb of the cell
+//             above and +rb of the cell below (formed here as those cells
+//             form them); then mu (first VJP) or the new lam (second VJP).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -491,43 +491,80 @@ __global__ void __launch_bounds__(kAdjThreads) adj_face_rev_kernel(AdjArgs A) {
   block_partial(xib, A.xpart + A.nblock);
 }
 
+// The slope cotangents of cell c along D: lb = (dh/dl) hb, rb = (dh/dr) hb
+// with hb = Pb - Mb (the cotangent of its half slope h).
 template <int NDIM, int D>
-__device__ __forceinline__ void a4_axis(const AdjArgs& A, long long c, const int x[3], double (&ub)[NDIM + 2]) {
+__device__ __forceinline__ void slope_cot(const AdjArgs& A, long long c, const int x[3],
+                                          double (&pb)[NDIM + 2], double (&mb)[NDIM + 2],
+                                          double (&lb)[NDIM + 2], double (&rb)[NDIM + 2]) {
   constexpr int NV = NDIM + 2;
-  double* Pb = A.Pb + (long long)D * NV * A.ncell;
-  double* Mb = A.Mb + (long long)D * NV * A.ncell;
+  const double* Pb = A.Pb + (long long)D * NV * A.ncell;
+  const double* Mb = A.Mb + (long long)D * NV * A.ncell;
   double um[NV], u0[NV], up[NV];
   load_nb<NV>(A, A.V, c, x, D, -1, um);
   load<NV>(A.V, A.ncell, c, u0);
   load_nb<NV>(A, A.V, c, x, D, 1, up);
-  const bool wlo = x[D] == 0 && A.refl_lo[D];
-  const bool whi = x[D] == A.n[D] - 1 && A.refl_hi[D];
-  double lb[NV], rb[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
-    const double pb = Pb[v * A.ncell + c], mb = Mb[v * A.ncell + c];
-    const double hb = pb - mb;
+    pb[v] = Pb[v * A.ncell + c];
+    mb[v] = Mb[v * A.ncell + c];
+    const double hb = pb[v] - mb[v];
     double dl, dr;
     mc_half_partials(u0[v] - um[v], up[v] - u0[v], dl, dr);
     lb[v] = dl * hb;
     rb[v] = dr * hb;
-    ub[v] += pb + mb + lb[v] - rb[v];
-    Pb[v * A.ncell + c] = lb[v];
-    Mb[v * A.ncell + c] = rb[v];
   }
-  // a wall's ghost neighbour is S of this cell: its share comes back here
-  if (wlo) {
+}
+
+// A4: U_bar += Pb + Mb + lb - rb of the cell itself (a wall's ghost
+// neighbour is S of this cell: its share comes back here).
+template <int NDIM, int D>
+__device__ __forceinline__ void a4_axis(const AdjArgs& A, long long c, const int x[3], double (&ub)[NDIM + 2]) {
+  constexpr int NV = NDIM + 2;
+  double pb[NV], mb[NV], lb[NV], rb[NV];
+  slope_cot<NDIM, D>(A, c, x, pb, mb, lb, rb);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) ub[v] += pb[v] + mb[v] + lb[v] - rb[v];
+  if (x[D] == 0 && A.refl_lo[D]) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) ub[v] -= (v == 1 + D) ? -lb[v] : lb[v];
   }
-  if (whi) {
+  if (x[D] == A.n[D] - 1 && A.refl_hi[D]) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) ub[v] += (v == 1 + D) ? -rb[v] : rb[v];
   }
 }
 
+// A5: U_bar gathers -lb of the cell above (its l is U_above - U_this) and
+// +rb of the cell below (its r is U_this - U_below), formed here as those
+// cells form them.
+template <int NDIM, int D>
+__device__ __forceinline__ void a5_axis(const AdjArgs& A, long long c, const int x[3], double (&ub)[NDIM + 2]) {
+  constexpr int NV = NDIM + 2;
+  double pb[NV], mb[NV], lb[NV], rb[NV];
+  bool neg;
+  if (x[D] + 1 < A.n[D] || !A.refl_hi[D]) {
+    const long long q = neighbour(A, c, x, D, 1, neg);
+    int xq[3] = {x[0], x[1], x[2]};
+    xq[D] = x[D] + 1 < A.n[D] ? x[D] + 1 : 0;
+    slope_cot<NDIM, D>(A, q, xq, pb, mb, lb, rb);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ub[v] -= lb[v];
+  }
+  if (x[D] > 0 || !A.refl_lo[D]) {
+    const long long q = neighbour(A, c, x, D, -1, neg);
+    int xq[3] = {x[0], x[1], x[2]};
+    xq[D] = x[D] > 0 ? x[D] - 1 : A.n[D] - 1;
+    slope_cot<NDIM, D>(A, q, xq, pb, mb, lb, rb);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ub[v] += rb[v];
+  }
+}
+
+// A4 and A5 of every axis in one pass (A4 of all axes first, then A5, the
+// order of the two passes they replace), then mu or the new lam.
 template <int NDIM>
-__global__ void __launch_bounds__(kAdjThreads) adj_slope_kernel(AdjArgs A) {
+__global__ void __launch_bounds__(kAdjThreads) adj_gather_kernel(AdjArgs A) {
   constexpr int NV = NDIM + 2;
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= A.ncell) return;
@@ -538,37 +575,6 @@ __global__ void __launch_bounds__(kAdjThreads) adj_slope_kernel(AdjArgs A) {
   a4_axis<NDIM, 0>(A, c, x, ub);
   if constexpr (NDIM >= 2) a4_axis<NDIM, 1>(A, c, x, ub);
   if constexpr (NDIM >= 3) a4_axis<NDIM, 2>(A, c, x, ub);
-#pragma unroll
-  for (int v = 0; v < NV; ++v) A.out[v * A.ncell + c] = ub[v];
-}
-
-template <int NDIM, int D>
-__device__ __forceinline__ void a5_axis(const AdjArgs& A, long long c, const int x[3], double (&ub)[NDIM + 2]) {
-  constexpr int NV = NDIM + 2;
-  const double* lbv = A.Pb + (long long)D * NV * A.ncell;
-  const double* rbv = A.Mb + (long long)D * NV * A.ncell;
-  bool neg;
-  if (x[D] + 1 < A.n[D] || !A.refl_hi[D]) {  // l of the cell above is U_above - U_this
-    const long long q = neighbour(A, c, x, D, 1, neg);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) ub[v] -= lbv[v * A.ncell + q];
-  }
-  if (x[D] > 0 || !A.refl_lo[D]) {  // r of the cell below is U_this - U_below
-    const long long q = neighbour(A, c, x, D, -1, neg);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) ub[v] += rbv[v * A.ncell + q];
-  }
-}
-
-template <int NDIM>
-__global__ void __launch_bounds__(kAdjThreads) adj_gather_kernel(AdjArgs A) {
-  constexpr int NV = NDIM + 2;
-  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= A.ncell) return;
-  int x[3];
-  cell_coords(A, c, x);
-  double ub[NV];
-  load<NV>(A.out, A.ncell, c, ub);
   a5_axis<NDIM, 0>(A, c, x, ub);
   if constexpr (NDIM >= 2) a5_axis<NDIM, 1>(A, c, x, ub);
   if constexpr (NDIM >= 3) a5_axis<NDIM, 2>(A, c, x, ub);
@@ -636,7 +642,6 @@ static hipError_t vjp_launch(AdjArgs A, int form, hipStream_t s) {
   hipError_t e = hipLaunchKernel(cell_kernel_ptr<NDIM>(form), grid, block, args, 0, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(adj_face_rev_kernel<NDIM>, grid, block, 0, s, A);
-  hipLaunchKernelGGL(adj_slope_kernel<NDIM>, grid, block, 0, s, A);
   hipLaunchKernelGGL(adj_gather_kernel<NDIM>, grid, block, 0, s, A);
   return hipGetLastError();
 }
