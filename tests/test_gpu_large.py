@@ -27,6 +27,7 @@ def test_state_past_4_gib():
     s.steps(U, 2)
     Ug = U.cpu().numpy()
     assert s.poll() == 0
+    dblk = s.diag(U)
     s.close()
     Uo, _, _ = oracle.run(cfg, Ub, 2)
     scale = [np.abs(Uo[0]).max()] * 4 + [np.abs(Uo[4]).max()]
@@ -42,7 +43,13 @@ def test_state_past_4_gib():
     s.steps(Ut, 2)
     torch.cuda.synchronize()
     assert s.poll() == 0
+    # the diagnostics of the whole state: sums are reps times the block's
+    # (to rounding of the summation order), maxima the block's exactly
+    dbig = s.diag(Ut)
     s.close()
+    for q in range(6):
+        assert abs(dbig[q] - reps * dblk[q]) <= 1e-12 * max(abs(reps * dblk[q]), reps * abs(dblk[0])), (q, dbig[q], dblk[q])
+    assert dbig[6] == dblk[6] and dbig[7] == dblk[7]
     ref = torch.from_numpy(Ug).cuda()
     copies = Ut.view(5, reps, 8, 256, 256)
     same = (copies == ref[:, None]).flatten(1).all(dim=1)
