@@ -33,6 +33,7 @@ def test_next_dt_is_the_cfl_dt_of_the_current_state(ndim, n):
     print(f"[case] cfl {ndim}D {n}", flush=True)
     U = torch.from_numpy(U0.copy()).cuda()
     s = R.Solver(cfg)
+    assert s.time() == (0.0, 0.0)  # no state recorded yet
     # a prime sets t and records the maxima of U
     s.prime(U, 0.25)
     t, dt = s.time()
