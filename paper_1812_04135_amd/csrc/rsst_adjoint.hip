@@ -67,6 +67,12 @@ struct AdjArgs {
   double* lam;
   double* mu;
   double dt;
+  // the second VJP's last pass also folds the xi partials of both VJPs into
+  // dJdxi (its workgroup 0, after its own cells)
+  const double* xp1;
+  const double* xp2;
+  int xm;
+  double* dJdxi;
 };
 
 __device__ __forceinline__ void cell_coords(const AdjArgs& A, long long c, int x[3]) {
@@ -561,13 +567,11 @@ __device__ __forceinline__ void a5_axis(const AdjArgs& A, long long c, const int
   }
 }
 
-// A4 and A5 of every axis in one pass (A4 of all axes first, then A5, the
+// A4 and A5 of every axis for cell c (A4 of all axes first, then A5, the
 // order of the two passes they replace), then mu or the new lam.
 template <int NDIM>
-__global__ void __launch_bounds__(kAdjThreads) adj_gather_kernel(AdjArgs A) {
+__device__ __forceinline__ void gather_cell(const AdjArgs& A, long long c) {
   constexpr int NV = NDIM + 2;
-  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= A.ncell) return;
   int x[3];
   cell_coords(A, c, x);
   double ub[NV];
@@ -597,9 +601,8 @@ __global__ void __launch_bounds__(kAdjThreads) adj_gather_kernel(AdjArgs A) {
 }
 
 // dJdxi += dt/2 (sum of the U1 partials) + dt (sum of the U partials), in a
-// fixed order.  One workgroup.
-__global__ void __launch_bounds__(kAdjThreads) adj_xi_kernel(const double* p1, const double* p2, int m, double dt,
-                                                            double* dJdxi) {
+// fixed order, by one workgroup (every thread of it calls this).
+__device__ __forceinline__ void xi_reduce(const double* p1, const double* p2, int m, double dt, double* dJdxi) {
   __shared__ double red[2][kAdjThreads / 64];
   double s1 = 0.0, s2 = 0.0;
   for (int q = threadIdx.x; q < m; q += kAdjThreads) {
@@ -621,6 +624,16 @@ __global__ void __launch_bounds__(kAdjThreads) adj_xi_kernel(const double* p1, c
     }
     *dJdxi += 0.5 * dt * a + dt * b;
   }
+}
+
+// The last pass of a VJP; in the second VJP its workgroup 0 also folds the
+// xi partials of both VJPs (complete: their passes ended before this one
+// began) into dJdxi, after its own cells.
+template <int NDIM>
+__global__ void __launch_bounds__(kAdjThreads) adj_gather_kernel(AdjArgs A) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < A.ncell) gather_cell<NDIM>(A, c);
+  if (A.post == 2 && blockIdx.x == 0) xi_reduce(A.xp1, A.xp2, A.xm, A.dt, A.dJdxi);
 }
 
 template <int NDIM>
@@ -687,10 +700,15 @@ hipError_t launch_adjoint_step(const AdjointPlan& p, const double* U, const doub
   double* part1 = mu + nf;
   double* part2 = part1 + 2 * nblock;
   A.nblock = nblock;
-  const dim3 eb(kAdjThreads);
   A.lam = lam;
   A.mu = mu;
   A.dt = dt;
+  // each VJP leaves partials of the f part then the alpha part (2 nblock
+  // each); the second VJP's last pass folds both sets into dJdxi
+  A.xp1 = part1;
+  A.xp2 = part2;
+  A.xm = 2 * nblock;
+  A.dJdxi = dJdxi;
   auto vjp = [&](const double* V, const double* Wc, double* out, double* part, int post) {
     A.V = V;
     A.W = Wc;
@@ -709,8 +727,6 @@ hipError_t launch_adjoint_step(const AdjointPlan& p, const double* U, const doub
   // (b, s2) = VJP(U, mu) with lam = lam/2 + mu + dt b formed by its last pass
   e = vjp(U, mu, ab, part2, 2);
   if (e != hipSuccess) return e;
-  // each VJP left partials of the f part then the alpha part: 2 nblock each
-  hipLaunchKernelGGL(adj_xi_kernel, dim3(1), eb, 0, s, part1, part2, 2 * nblock, dt, dJdxi);
   return hipGetLastError();
 }
 
