@@ -22,8 +22,12 @@
 //     planes of its own column in registers, so every z face is computed
 //     once and z needs no exchange at all;
 //   * every face state (U +- sigma/2, its pressure, c_tot and normal
-//     velocity) is computed once, by the cell that owns it; each face flux
-//     is computed once, by the cell above it, and handed to the cell below.
+//     velocity) is computed once, by the cell that owns it; a z flux (the
+//     marched axis) is computed once and carried to the next plane, an
+//     interior x flux once and handed to the lane above by DPP; the x flux at
+//     a wave edge is formed by both waves that share it, and a y flux inside
+//     a 3D tile by both rows (the same face states and code, so the same
+//     bits), and the y flux at a tile's outer face by each of the two tiles.
 //   * workgroup ids are remapped so that consecutive tiles (which share
 //     halo rows) run on the same XCD and share its L2.
 #include <cstdlib>
@@ -200,7 +204,9 @@ Geometry plan_geometry(int ndim, const int n[3]) {
     // about a microsecond and a half however few cells it holds (a wave runs
     // ~1000 dependent instructions per plane), so a small grid is fastest as
     // many short marches, although each chunk re-reads 4 planes and forms one
-    // extra face to start; RSST_KM overrides the chunk length (tuning)
+    // extra face to start.  The environment variable RSST_KM, read when a
+    // solver is made, sets the chunk length instead: the results do not
+    // depend on it, which a GPU test checks for several lengths
     const long long want = ndim == 3 ? 256 : 512;
     int km = ndim == 3 ? 128 : 64;
     const int kmin = 1;

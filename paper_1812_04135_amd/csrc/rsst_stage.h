@@ -107,12 +107,8 @@ __device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, int voff, i
 // L2 holds the rows that neighbouring tiles share (256^3 FP64: 21% fewer
 // stage-2 HBM reads).  1D and 2D grids, and the batch, whose states are
 // re-read from L2/MALL by the next stage, keep the default policy.
-#ifndef RSST_ST_AUX
-#define RSST_ST_AUX 2
-#endif
-#ifndef RSST_UN_AUX
-#define RSST_UN_AUX 2
-#endif
+constexpr int kStoreAux3 = 2;  // 3D stage outputs: non-temporal
+constexpr int kUnAux3 = 2;     // 3D stage 2's pointwise step-start reads: non-temporal
 
 template <typename ST, int AUX = 0>
 __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, int voff, int soff, ST x) {
@@ -272,20 +268,14 @@ __host__ __device__ inline Carve carve(int ndim, int ts, int nwx) {
   c.seamP = o;  o += ts * nwx * PL;                       // lane 63 plus-face states
   c.seamPl = o; o += ts * PL;                             // last cell's plus-face state
   c.red = o;    o += 16;
-#ifdef RSST_LDS_PAD
-  if (ndim == 3) o += RSST_LDS_PAD;  // tuning experiments only
-#endif
   c.total = o;
   return c;
 }
 
 // Rows per 3D tile for a row of nwx waves (512 threads at most).  Rows of
 // 257-512 cells run as rows of 8 waves, one row per tile.
-#ifndef RSST_TS_WIDE
-#define RSST_TS_WIDE 2
-#endif
 __host__ __device__ constexpr int tile_rows(int nwx) {
-  return nwx == 1 ? 8 : (nwx == 2 ? 4 : (nwx <= 4 ? RSST_TS_WIDE : 1));
+  return nwx == 1 ? 8 : (nwx == 2 ? 4 : (nwx <= 4 ? 2 : 1));
 }
 
 // A 1D cell kept in registers across stages (steps1d_kernel): the stage
@@ -509,7 +499,7 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
       }
     }
     if constexpr (HM) load_cell_raw<NDIM, ST>(uin, q2k, col, q2r);
-    if constexpr (STAGE == 2 && !REG) load_cell_raw<NDIM, ST, HS ? RSST_UN_AUX : 0>(unp, k, col, unr);
+    if constexpr (STAGE == 2 && !REG) load_cell_raw<NDIM, ST, HS ? kUnAux3 : 0>(unp, k, col, unr);
 
     // ---- P1: publish this plane's cell state
     if constexpr (HS) {
@@ -696,6 +686,15 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
           for (int v = 0; v < NV; ++v) Fx_hi[v] = Fe[v];
         }
       }
+      // A row of 64 m + 1 cells ends in lane 0 of its last wave: that lane
+      // took its left face above and forms the row's end face here.
+      if (lane == 0 && last_x && !wave_idle) {
+        Face<NV> fl, fr;
+        get_face(seamPl + row * PL, 1, fl);
+        if (x_per) get_face(seamM + (row * nwx) * PL, 1, fr);
+        else fr = mirror<NDIM, 0>(fl);
+        flux2<NDIM, 0>(fl, fr, Fx_hi);
+      }
 #pragma unroll
       for (int v = 0; v < NV; ++v) Dl[v] = -(Fx_hi[v] - Fx_lo[v]) * hx;
     }
@@ -764,7 +763,7 @@ __device__ __forceinline__ double stage_body(const StageArgs& A, double* lds, in
         if constexpr (REG) {
           rc->st[v] = (double)st;
         } else {
-          buf_store<ST, HS ? RSST_ST_AUX : 0>(uout.rsrc(v, k), col, uout.soff(v, k), st);
+          buf_store<ST, HS ? kStoreAux3 : 0>(uout.rsrc(v, k), col, uout.soff(v, k), st);
         }
         out[v] = (double)st + bgv;
         if constexpr (REG) rc->out[v] = out[v];

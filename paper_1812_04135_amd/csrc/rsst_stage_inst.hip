@@ -21,18 +21,14 @@ namespace rsstk {
 
 // FORM: the correction form, plus kExtCmax when xi follows the sound speed
 // (eq. cx), kExtVdw for the van der Waals gas, kExtHydro for hydrostatic walls.
-#ifndef RSST_LB3
-#define RSST_LB3 512
-#endif
-#ifndef RSST_WPE3
-#define RSST_WPE3 1
-#endif
+// 3D workgroups are at most 512 threads (8 waves at ~200 VGPRs, two waves per
+// SIMD); 1D and 2D rows take up to 1024.
+constexpr int kMaxThreads3 = 512;
 
 constexpr bool kBig = RSST_INST_BIG != 0;
 
 template <int NDIM, int STAGE, typename ST, int FORM, int NWXC, bool BIG>
-__global__ void __launch_bounds__(NDIM == 3 ? RSST_LB3 : 1024)
-    __attribute__((amdgpu_waves_per_eu(NDIM == 3 ? RSST_WPE3 : 1))) stage_kernel(const StageArgs A) {
+__global__ void __launch_bounds__(NDIM == 3 ? kMaxThreads3 : 1024) stage_kernel(const StageArgs A) {
   extern __shared__ double lds[];
   const Geometry& G = A.geo;
   const int L = xcd_tile(blockIdx.x, gridDim.x);

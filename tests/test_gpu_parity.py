@@ -104,6 +104,15 @@ CASES = [
     (3, [40, 10, 7], ["reflect"] * 3, None, "euler"),
     (3, [300, 5, 6], ["periodic", "reflect", "reflect"], [0.0, 0.3, -0.5], "pvs"),  # 5 of 8 waves
     (3, [512, 4, 5], ["reflect", "periodic", "periodic"], None, "pms"),  # widest 3D row
+    # rows of 64 m + 1 cells: the row's last cell is lane 0 of its last wave,
+    # which forms both of its x faces
+    (1, [65], ["periodic"], None, "pvs"),
+    (1, [129], ["reflect"], [0.2], "pd"),
+    (2, [65, 10], ["periodic", "reflect"], [0.0, -0.5], "pvs"),
+    (2, [193, 6], ["reflect", "periodic"], None, "pms"),
+    (3, [65, 6, 5], ["periodic", "periodic", "reflect"], [0.0, 0.0, -0.5], "pvs"),
+    (3, [129, 5, 4], ["reflect", "periodic", "periodic"], None, "dvs"),
+    (3, [257, 4, 4], ["periodic"] * 3, None, "pvs"),
 ]
 
 
