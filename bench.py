@@ -102,7 +102,11 @@ def bench_batch(R, W, np, torch, stream, args):
             starts = [U for _, U, _ in boxes]
         U0 = B.pack(starts)
         U = torch.empty_like(U0)
-        tiles, tune_ms, cached = B.autotune(U0, nsteps=20)
+        if args.batch_tiles:
+            tiles, cached = [int(x) for x in args.batch_tiles.split(",")], False
+            B.set_tiles(tiles)
+        else:
+            tiles, tune_ms, cached = B.autotune(U0, nsteps=20)
         U.copy_(U0)
         B.run(U, nst, stream)  # warm
         ms = []
@@ -323,6 +327,10 @@ def main():
     ap.add_argument("--no-rt", action="store_true", help="skip the Rayleigh-Taylor workload")
     ap.add_argument("--no-conv", action="store_true", help="skip the linear-wave convergence runs")
     ap.add_argument("--adjoint-steps", type=int, default=400)
+    ap.add_argument("--only", choices=["batch", "adjoint"], default=None,
+                    help="run only that secondary workload and print its JSON (for profiling)")
+    ap.add_argument("--batch-tiles", default=None,
+                    help="strip rows per width class, e.g. 32,64,96,96 (skips the autotuner)")
     ap.add_argument("--copy-ref", action="store_true",
                     help="only run a plain device copy of one 256^3 FP64 state (5 x 134 MB), "
                          "the reference kernel for scaling HBM byte counters")
@@ -340,6 +348,11 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.only:
+        stream = torch.cuda.current_stream()
+        leg = bench_batch if args.only == "batch" else bench_adjoint
+        print(json.dumps(leg(R, W, np, torch, stream, args)), flush=True)
+        return
     if args.copy_ref:
         x = torch.ones(5 * 256 ** 3, dtype=torch.float64, device=dev)
         y = torch.empty_like(x)

@@ -256,8 +256,25 @@ int rsst_batch_run(rsst_batch h, void* U_all, int nsteps, void* stream);
 /* Synchronises, then copies the time reached by every box into t[nbox]. */
 int rsst_batch_times(rsst_batch h, double* t, void* stream);
 
-/* As rsst_poll, for the batch. */
+/* As rsst_poll, for the batch, with one more flag: bit 3 (8) is set when a
+ * work item gave up waiting for a dependency (see rsst_batch_set_wait_limit);
+ * then the call returns RSST_E_DEVICE and the run's results are invalid. */
 int rsst_batch_poll(rsst_batch h, uint32_t* flags);
+
+/* Longest time, in seconds (0 to 3600; default 10), that a work item of a
+ * run waits for the items it depends on.  Past it the item is skipped
+ * (nothing computed or stored, but marked done, so every workgroup drains
+ * and the kernel ends) and the run is flagged for rsst_batch_poll: a
+ * dependency that never arrives ends the run with an error instead of a
+ * hang.  Takes effect at the next run.  A limit of 0 gives up on any wait
+ * that is not satisfied at once, which tests of the error path use. */
+int rsst_batch_set_wait_limit(rsst_batch h, double seconds);
+
+/* Synchronises, then sets the time of every box to t[nbox] (host array) and
+ * the latched non-physical flags to `flags` (bits as rsst_poll reports
+ * them).  For callers that advance the batch on scratch data and restore the
+ * record afterwards, as the strip-row autotuner does. */
+int rsst_batch_set_times(rsst_batch h, const double* t, uint32_t flags, void* stream);
 
 int rsst_batch_destroy(rsst_batch h);
 

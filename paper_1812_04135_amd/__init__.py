@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librsst.so")
 
 RSST_OK = 0
+RSST_E_DEVICE = -3
 RSST_E_NONPHYSICAL = -5
 FORMS = {"euler": 0, "pvs": 1, "pms": 2, "dvs": 3, "dms": 4, "pd": 5}
 BCS = {"periodic": 0, "reflect": 1, "hydro": 2}
@@ -77,6 +78,8 @@ def lib():
                                       ctypes.POINTER(ctypes.c_int64), ctypes.c_int, vp,
                                       ctypes.POINTER(vp)]
         L.rsst_batch_set_tiles.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+        L.rsst_batch_set_times.argtypes = [vp, dp, ctypes.c_uint32, vp]
+        L.rsst_batch_set_wait_limit.argtypes = [vp, ctypes.c_double]
         L.rsst_batch_get_tiles.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
         L.rsst_batch_run.argtypes = [vp, vp, ctypes.c_int, vp]
         L.rsst_batch_times.argtypes = [vp, dp, vp]
@@ -321,15 +324,35 @@ def rsst_batch_times(h, nbox: int, stream=None) -> np.ndarray:
     return t
 
 
+def rsst_batch_poll_raw(h) -> int:
+    """The batch's flag word (cleared on the device), without raising."""
+    f = ctypes.c_uint32()
+    code = lib().rsst_batch_poll(h, ctypes.byref(f))
+    if code not in (RSST_OK, RSST_E_NONPHYSICAL) and not (code == RSST_E_DEVICE and f.value & 8):
+        _check(code, "rsst_batch_poll")
+    return f.value
+
+
 def rsst_batch_poll(h) -> int:
     f = ctypes.c_uint32()
     code = lib().rsst_batch_poll(h, ctypes.byref(f))
-    if code == RSST_E_NONPHYSICAL:
+    if code == RSST_E_NONPHYSICAL or (code == RSST_E_DEVICE and f.value & 8):
         err = RsstError(code, "rsst_batch_poll")
         err.flags = f.value
         raise err
     _check(code, "rsst_batch_poll")
     return f.value
+
+
+def rsst_batch_set_wait_limit(h, seconds: float):
+    _check(lib().rsst_batch_set_wait_limit(h, float(seconds)), "rsst_batch_set_wait_limit")
+
+
+def rsst_batch_set_times(h, t, flags: int = 0, stream=None):
+    tt = np.ascontiguousarray(t, dtype=np.float64)
+    _check(lib().rsst_batch_set_times(h, tt.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      ctypes.c_uint32(int(flags)), _stream(stream)),
+           "rsst_batch_set_times")
 
 
 def rsst_batch_destroy(h):
@@ -397,6 +420,12 @@ class Batch:
 
     def poll(self):
         return rsst_batch_poll(self.h)
+
+    def set_wait_limit(self, seconds):
+        rsst_batch_set_wait_limit(self.h, seconds)
+
+    def set_times(self, t, flags=0, stream=None):
+        rsst_batch_set_times(self.h, t, flags, stream)
 
     def close(self):
         if self.h is not None:

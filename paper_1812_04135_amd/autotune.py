@@ -80,6 +80,11 @@ def tune(batch, U, nsteps: int = 20, candidates=CANDIDATES, reps: int = 2, cache
         return tiles, float(db[key]["ms"]), True
     nsteps = max(1, min(int(nsteps), batch.max_steps))
     present = sorted({width_class(s[2]) for s in batch.shapes})
+    # the runs below advance the per-box times and may latch flags: keep the
+    # batch's record and put it back afterwards
+    from . import rsst_batch_poll_raw, rsst_batch_set_times
+    times0 = batch.times(stream)
+    flags0 = rsst_batch_poll_raw(batch.h)
     scratch = torch.empty_like(U)
     tiles = list(batch.tiles())
     times = {}
@@ -104,6 +109,7 @@ def tune(batch, U, nsteps: int = 20, candidates=CANDIDATES, reps: int = 2, cache
                 best, tiles = ms, t
     batch.set_tiles(tiles)
     del scratch
+    rsst_batch_set_times(batch.h, times0, flags0, stream)
     if cache:
         db = _load(cache)
         db[key] = {"strip_rows": tiles, "ms": best, "nsteps": nsteps}

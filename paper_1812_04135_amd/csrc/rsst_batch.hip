@@ -35,6 +35,7 @@
 namespace rsstk {
 
 constexpr int kBatchThreads = 256;  // one box row: at most 4 waves
+constexpr int kBatchPerCU = 2;      // persistent workgroups per CU
 
 struct BoxDev {
   StageArgs s1, s2;  // stage views of the box (pointers into U_all / U1_all)
@@ -64,14 +65,26 @@ struct BatchState {
   unsigned* flags;               // non-physical flags
   int nbox, nitem, nsteps, max_steps;
   unsigned total;                // 2 nsteps nitem tickets
+  unsigned long long wait_ticks; // longest dependency wait, in wall-clock ticks (100 MHz)
 };
 
 __device__ __forceinline__ unsigned ld_acquire(const unsigned* p) {
   return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ void wait_at_least(const unsigned* p, unsigned v) {
-  while (ld_acquire(p) < v) __builtin_amdgcn_s_sleep(2);
+// Flag bit of a run whose queue gave up on a dependency wait (reported by
+// rsst_batch_poll as RSST_E_DEVICE): a wait past its deadline means a
+// dependency that will not arrive, so instead of spinning for ever the item
+// is skipped (marked done, nothing stored) and every workgroup drains.
+constexpr unsigned kQueueTimeout = 8u;
+
+// Spins until *p >= v or the wall clock passes `deadline`; false on timeout.
+__device__ __forceinline__ bool wait_at_least(const unsigned* p, unsigned v, unsigned long long deadline) {
+  while (ld_acquire(p) < v) {
+    if (wall_clock64() > deadline) return false;
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return true;
 }
 
 // Clears the per-run counters (graph-safe: a kernel, not a memset node).
@@ -151,7 +164,7 @@ __global__ void __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per
                                                             const Item* __restrict__ items,
                                                             BatchState S) {
   extern __shared__ double lds[];
-  __shared__ unsigned tshare;
+  __shared__ unsigned tshare, skip;
   __shared__ double red[kBatchThreads / 64];
   const int tid = threadIdx.x;
   Pending prev{-1, 0, 0, 0u, 0u, false, 0.0};
@@ -166,25 +179,39 @@ __global__ void __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per
     if (t >= S.total) break;
     const int q = (int)(t / (unsigned)S.nitem), r = (int)(t % (unsigned)S.nitem);
     const Item it = items[r];
-    const int b = it.box, p = it.blk, n = q >> 1;
+    // box and block are workgroup-uniform: said explicitly, every field of
+    // the box's stage views stays in scalar registers (otherwise the compiler
+    // wraps each buffer access built from them in a per-lane waterfall loop)
+    const int b = __builtin_amdgcn_readfirstlane(it.box), p = __builtin_amdgcn_readfirstlane(it.blk), n = q >> 1;
     const bool st2 = (q & 1) != 0;
     const BoxDev& B = boxes[b];
     if (tid == 0) {
-      if (!st2 && n > 0) wait_at_least(S.cnt2 + (long long)b * S.max_steps + (n - 1), (unsigned)B.nblk);
+      const unsigned long long deadline = wall_clock64() + S.wait_ticks;
+      bool ok = true;
+      if (!st2 && n > 0)
+        ok = wait_at_least(S.cnt2 + (long long)b * S.max_steps + (n - 1), (unsigned)B.nblk, deadline);
       if (q > 0) {
         const unsigned* dq = S.done + (long long)(q - 1) * S.nitem + B.rbase;
-        for (int d = 0; d < it.ndep; ++d) wait_at_least(dq + it.dep[d], 1u);
+        for (int d = 0; d < it.ndep && ok; ++d) ok = wait_at_least(dq + it.dep[d], 1u, deadline);
       }
+      if (!ok) atomicOr(S.flags, kQueueTimeout);
+      skip = ok ? 0u : 1u;
     }
     __syncthreads();
+    const bool skip_item = __builtin_amdgcn_readfirstlane(skip) != 0u;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const unsigned long long mb = __hip_atomic_load(S.maxbits + (long long)b * (S.max_steps + 1) + n,
                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const double dt = B.cfl_h / __longlong_as_double((long long)mb);
     unsigned bad = 0;
-    double cmax;
-    if (!st2) cmax = stage_body<2, 1, ST, FORM, 0>(B.s1, lds, 0, p * B.groups, dt, bad);
-    else cmax = stage_body<2, 2, ST, FORM, 0>(B.s2, lds, 0, p * B.groups, dt, bad);
+    double cmax = 0.0;
+    if (skip_item) {
+      // nothing computed or stored; the item is still signalled done below
+    } else if (!st2) {
+      cmax = stage_body<2, 1, ST, FORM, 0>(B.s1, lds, 0, p * B.groups, dt, bad);
+    } else {
+      cmax = stage_body<2, 2, ST, FORM, 0>(B.s2, lds, 0, p * B.groups, dt, bad);
+    }
     if (bad) atomicOr(S.flags, bad);
     if (st2) {
       const double wm = wave_max(cmax);
@@ -243,6 +270,7 @@ struct rsst_batch_s {
   int cap_steps;
   bool dirty;
   int grid;
+  unsigned long long wait_ticks;  // dependency-wait limit of the queue (100 MHz ticks)
 };
 
 static int batch_validate(const rsst_config* c, int nbox, const int64_t* off) {
@@ -398,6 +426,7 @@ static hipError_t batch_launch_all(rsst_batch_s* h, hipStream_t s, int nsteps) {
   S.nsteps = nsteps;
   S.max_steps = h->max_steps;
   S.total = (unsigned)(2ll * nsteps * h->nitem);
+  S.wait_ticks = h->wait_ticks;
   hipLaunchKernelGGL(batch_reset_kernel, dim3(256), dim3(256), 0, s, S);
   const int bpb = 8;
   hipLaunchKernelGGL(batch_prime_kernel<ST>, dim3(h->nbox * bpb), dim3(256), 0, s, h->d_boxes, S, bpb);
@@ -426,6 +455,9 @@ static int batch_prepare(rsst_batch_s* h, void* U, int nsteps) {
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return RSST_E_DEVICE;
+  // at most kBatchPerCU workgroups per CU: more of them (4 fit) make every
+  // run slower (more items in flight, each slower)
+  if (per_cu > kBatchPerCU) per_cu = kBatchPerCU;
   h->grid = (per_cu > 0 ? per_cu : 1) * ncu;
   // capture reset + prime + persistent kernel in one graph
   if (h->exec) {
@@ -474,6 +506,7 @@ int rsst_batch_init(const rsst_config* boxes, int nbox, const int64_t* offsets, 
     if (end > h->total_elems) h->total_elems = end;
   }
   h->strip[0] = h->strip[1] = h->strip[2] = h->strip[3] = 16;
+  h->wait_ticks = 1000000000ull;  // 10 s
   // size item tables for the shortest strips the tile setter accepts (8 rows)
   long long cap_items = 0;
   for (int b = 0; b < nbox; ++b) {
@@ -574,6 +607,23 @@ int rsst_batch_times(rsst_batch h, double* t, void* stream) {
              : RSST_E_DEVICE;
 }
 
+int rsst_batch_set_wait_limit(rsst_batch h, double seconds) {
+  if (!h || !(seconds >= 0.0) || !(seconds <= 3600.0)) return RSST_E_ARG;
+  h->wait_ticks = (unsigned long long)(seconds * 1e8);
+  h->dirty = true;
+  return RSST_OK;
+}
+
+int rsst_batch_set_times(rsst_batch h, const double* t, uint32_t flags, void* stream) {
+  if (!h || !t) return RSST_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipStreamSynchronize(s) != hipSuccess) return RSST_E_DEVICE;
+  if (hipMemcpy(h->d_tacc, t, sizeof(double) * h->nbox, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h->d_flags, &flags, sizeof(flags), hipMemcpyHostToDevice) != hipSuccess)
+    return RSST_E_DEVICE;
+  return RSST_OK;
+}
+
 int rsst_batch_poll(rsst_batch h, uint32_t* flags) {
   if (!h) return RSST_E_ARG;
   if (hipDeviceSynchronize() != hipSuccess) return RSST_E_DEVICE;
@@ -584,6 +634,7 @@ int rsst_batch_poll(rsst_batch h, uint32_t* flags) {
     if (hipMemcpy(h->d_flags, &z, sizeof(z), hipMemcpyHostToDevice) != hipSuccess) return RSST_E_DEVICE;
   }
   if (flags) *flags = f;
+  if (f & kQueueTimeout) return RSST_E_DEVICE;
   return f ? RSST_E_NONPHYSICAL : RSST_OK;
 }
 

@@ -32,7 +32,9 @@ def _boxes_fp64():
     out = []
     specs = [(16, 12, 3.0, "reflect"), (70, 33, 1.0, "reflect"), (130, 40, 12.0, "periodic"),
              (200, 24, 30.0, "reflect"), (64, 64, 5.0, "periodic"), (37, 9, 2.0, "periodic"),
-             (200, 33, 8.0, "periodic")]
+             (200, 33, 8.0, "periodic"),
+             # rows of 64 m + 1 cells (the last cell is lane 0 of the last wave)
+             (65, 20, 4.0, "reflect"), (193, 14, 6.0, "periodic")]
     for q, (nx, ny, xi, ybc) in enumerate(specs):
         g = [0.0, -0.5] if ybc == "reflect" else [0.0, 0.0]
         cfg, U = W.random_state(2, [nx, ny], seed_k=500 + q, xi=xi, form="pvs",
@@ -141,6 +143,9 @@ def test_autotuner_sets_tiles_caches_and_keeps_results(tmp_path):
     assert not cached and ms > 0
     assert torch.equal(U, U0)
     assert B.tiles() == tiles
+    # the tuning runs (on a scratch copy) leave the per-box times and flags as they were
+    assert np.all(B.times() == 0.0)
+    assert B.poll() == 0
     import json
     db = json.load(open(cache))
     assert db[autotune.batch_key(B)]["strip_rows"] == tiles
@@ -150,9 +155,11 @@ def test_autotuner_sets_tiles_caches_and_keeps_results(tmp_path):
     B.run(U, 5)
     torch.cuda.synchronize()
     outs = B.unpack(U)
+    times = B.times()
     for q, ((cfg, U0n), Ub) in enumerate(zip(boxes, outs)):
-        Us, _ = _single(cfg, U0n, 5)
+        Us, ts = _single(cfg, U0n, 5)
         assert np.array_equal(Ub, Us), q
+        assert times[q] == ts, q
 
 
 def test_batch_full_size_sampled_boxes():
@@ -182,3 +189,36 @@ def test_batch_full_size_sampled_boxes():
         err = max(float(np.abs(outs[q][v].astype(np.float64) - pert[v]).max() / s[v]) for v in range(4))
         print(f"[batch full] box {q} N={cfg['n'][0]} xi={cfg['xi']:.2f} err/|pert| = {err:.2e}", flush=True)
         assert err <= 1e-5, (q, err)
+
+
+def test_batch_wait_limit_gives_up_drains_and_recovers():
+    """A dependency wait past its limit ends the run with an error instead of
+    spinning: with a limit of 0 every wait not satisfied at once gives up, the
+    items are skipped but signalled, every workgroup drains and the kernel
+    ends; the poll reports the queue flag as RSST_E_DEVICE.  With the limit
+    restored the next run is exact again (bitwise the single-box runs)."""
+    boxes = _boxes_fp64()
+    nsteps = 6
+    B = R.Batch([c for c, _ in boxes], max_steps=8)
+    B.set_tiles([8, 8, 8, 8])
+    U0 = B.pack([u for _, u in boxes])
+    U = U0.clone()
+    B.set_wait_limit(0.0)
+    B.run(U, nsteps)
+    torch.cuda.synchronize()
+    with pytest.raises(R.RsstError) as e:
+        B.poll()
+    assert e.value.code == R.RSST_E_DEVICE and (e.value.flags & 8), (e.value.code, e.value.flags)
+    assert B.poll() == 0  # cleared
+    B.set_wait_limit(10.0)
+    U.copy_(U0)
+    B.set_times(np.zeros(len(boxes)))
+    B.run(U, nsteps)
+    torch.cuda.synchronize()
+    assert B.poll() == 0
+    outs = B.unpack(U)
+    times = B.times()
+    for q, ((cfg, U0n), Ub) in enumerate(zip(boxes, outs)):
+        Us, ts = _single(cfg, U0n, nsteps)
+        assert np.array_equal(Ub, Us), q
+        assert times[q] == ts, q
