@@ -49,7 +49,9 @@ enum rsst_status {
   RSST_E_NOMEM = -2,        /* device allocation failed                     */
   RSST_E_DEVICE = -3,       /* a HIP runtime call failed                    */
   RSST_E_UNSUPPORTED = -4,  /* valid but not supported by this build        */
-  RSST_E_NONPHYSICAL = -5   /* rho <= 0, P <= 0 or a non-finite value seen  */
+  RSST_E_NONPHYSICAL = -5,  /* rho <= 0, P <= 0 or a non-finite value seen  */
+  RSST_E_SCRATCH = -6       /* state beyond the fixed scratch of
+                               rsst_step_noalloc                            */
 };
 
 enum rsst_form { RSST_EULER = 0, RSST_PVS = 1, RSST_PMS = 2, RSST_DVS = 3,
@@ -189,6 +191,29 @@ int rsst_poll(rsst_handle h, uint32_t* flags);
 
 /* Frees the workspace.  The caller's arrays are untouched. */
 int rsst_destroy(rsst_handle h);
+
+/* ---- One step that allocates nothing --------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * step as rsst_step on a fresh handle (the same kernels, so the same bits):
+ * U advances by one SSP-RK2 step from t = 0 with dt_fixed > 0, or with the
+ * CFL dt of U formed on the device when dt_fixed <= 0.  No handle: cfg is
+ * validated on the host as by rsst_init (RSST_E_ARG), and RSST_WITH_ADJOINT
+ * or t_end != 0 give RSST_E_UNSUPPORTED (the time and the maxima are not
+ * kept between calls).  U: caller-owned device state as for rsst_step.
+ * flags: NULL, or a caller-owned device word that receives the step's
+ * non-physical flags (as rsst_poll's).  Scratch (device scalars, CFL maxima
+ * and the stage buffer U1) is a fixed 64 MiB device array of the library,
+ * held by each device it runs on until the process ends.  It takes a copy
+ * of the state, nvar * ncell * sizeof(value) bytes, plus 256 B of scalars
+ * and 8 B per stage-kernel workgroup (each part rounded up to 256 B); a
+ * configuration that needs more than 64 MiB (a 2D 1024^2 FP64 state needs
+ * 32 MiB, a 3D 128^3 FP32 perturbation 40 MiB) gives RSST_E_SCRATCH before
+ * any device call.  Calls no allocating routine; enqueues only
+ * (graph-capturable).
+ * All calls on one device share that scratch: calls that overlap on one
+ * device race, so order them on one stream. */
+int rsst_step_noalloc(const rsst_config* cfg, void* U, double dt_fixed, uint32_t* flags, void* stream);
 
 /* ---- Adjoint -------------------------------------------------------------
  * Discrete adjoint of one rsst_step of fixed dt (dt frozen: the CFL rule is

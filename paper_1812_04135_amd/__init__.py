@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "librsst.so")
 RSST_OK = 0
 RSST_E_DEVICE = -3
 RSST_E_NONPHYSICAL = -5
+RSST_E_SCRATCH = -6
 FORMS = {"euler": 0, "pvs": 1, "pms": 2, "dvs": 3, "dms": 4, "pd": 5}
 BCS = {"periodic": 0, "reflect": 1, "hydro": 2}
 PRECS = {"fp64": 0, "fp32_pert": 1}
@@ -65,6 +66,7 @@ def lib():
         L.rsst_init.argtypes = [ctypes.POINTER(rsst_config), vp, ctypes.POINTER(vp)]
         L.rsst_prime.argtypes = [vp, vp, ctypes.c_double, vp]
         L.rsst_step.argtypes = [vp, vp, ctypes.c_double, vp]
+        L.rsst_step_noalloc.argtypes = [ctypes.POINTER(rsst_config), vp, ctypes.c_double, vp, vp]
         L.rsst_stage.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double, vp]
         L.rsst_steps.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double, vp]
         L.rsst_get_time.argtypes = [vp, dp, dp, vp]
@@ -173,6 +175,14 @@ def rsst_prime(h, U, t0: float = 0.0, stream=None):
 
 def rsst_step(h, U, dt_fixed: float = 0.0, stream=None):
     _check(lib().rsst_step(h, _ptr(U), float(dt_fixed), _stream(stream)), "rsst_step")
+
+
+def rsst_step_noalloc(cfg: rsst_config, U, dt_fixed: float = 0.0, flags=None, stream=None):
+    """One step with no allocation (fixed library scratch); flags: None or a
+    one-element int32/uint32 device tensor that receives the step's flags."""
+    _check(lib().rsst_step_noalloc(ctypes.byref(cfg), _ptr(U), float(dt_fixed),
+                                   _ptr(flags) if flags is not None else None, _stream(stream)),
+           "rsst_step_noalloc")
 
 
 def rsst_stage(h, U, stage: int, dt_fixed: float = 0.0, stream=None):

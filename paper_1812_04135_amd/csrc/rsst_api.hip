@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <atomic>
 #include <new>
 #include <vector>
 
@@ -102,41 +103,12 @@ static int validate(const rsst_config* c) {
   return RSST_OK;
 }
 
-extern "C" {
-
-const char* rsst_strerror(int s) {
-  switch (s) {
-    case RSST_OK: return "success";
-    case RSST_E_ARG: return "invalid argument or configuration";
-    case RSST_E_NOMEM: return "device allocation failed";
-    case RSST_E_DEVICE: return "HIP runtime call failed";
-    case RSST_E_UNSUPPORTED: return "configuration not supported by this build";
-    case RSST_E_NONPHYSICAL: return "non-physical state (rho <= 0, P <= 0 or non-finite)";
-    default: return "unknown status";
-  }
-}
-
-const char* rsst_version(void) { return "rsst-gfx950 stage-v15"; }
-
-int rsst_init(const rsst_config* cfg, void* stream, rsst_handle* out) {
-  if (!out) return RSST_E_ARG;
-  *out = nullptr;
-  int st = validate(cfg);
-  if (st != RSST_OK) return st;
-  hipStream_t s = (hipStream_t)stream;
-
-  rsst_solver* h = new (std::nothrow) rsst_solver();
-  if (!h) return RSST_E_NOMEM;
-  h->cfg = *cfg;
-  h->nv = cfg->ndim + 2;
-  h->ncell = (long long)cfg->n[0] * cfg->n[1] * cfg->n[2];
-  h->elem = cfg->prec == RSST_FP32_PERT ? sizeof(float) : sizeof(double);
-  if (hipGetDevice(&h->device) != hipSuccess) { delete h; return RSST_E_DEVICE; }
-
-  StageArgs& a = h->args;
+// Kernel arguments of a validated configuration (no device call).  The
+// state, scalar and maxima pointers are left for the caller to set.
+static void fill_args(const rsst_config* cfg, long long ncell, StageArgs& a) {
   std::memset(&a, 0, sizeof(a));
   a.geo = rsstk::plan_geometry(cfg->ndim, cfg->n);
-  a.ncell = h->ncell;
+  a.ncell = ncell;
   for (int d = 0; d < 3; ++d) {
     a.bc_lo[d] = cfg->bc_lo[d];
     a.bc_hi[d] = cfg->bc_hi[d];
@@ -172,13 +144,88 @@ int rsst_init(const rsst_config* cfg, void* stream, rsst_handle* out) {
   a.bg_axis = cfg->prec == RSST_FP32_PERT ? cfg->bg_axis : -1;
   a.nbg = (a.bg_axis >= 0) ? cfg->n[a.bg_axis] : 1;
   a.bg_uniform = (a.bg_axis == -1 || (cfg->ndim >= 2 && a.bg_axis == cfg->ndim - 1)) ? 1 : 0;
+  a.nblk = a.geo.ntile_s * a.geo.nchunk;
+  a.big = (cfg->ndim == 3 && (long long)(cfg->ndim + 2) * ncell *
+                                 (long long)(cfg->prec == RSST_FP32_PERT ? 4 : 8) >= (1ll << 31)) ? 1 : 0;
+}
 
+// ---- rsst_step_noalloc: one step with no allocation ------------------------
+// Its scratch (device scalars, per-workgroup CFL maxima, the stage buffer U1)
+// lives in one file-scope device array of fixed size instead of a handle's
+// workspace.  Each device holds its own copy for the life of the process;
+// every call on a device reuses it, so calls that overlap on one device race.
+// In host code `scratch` only names the symbol: its device address, per
+// device, comes from hipGetSymbolAddress (taken once per device, with that
+// device current) and only that address reaches the kernels.
+static constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static constexpr int kMaxDevices = 64;
+static std::atomic<unsigned char*> g_scratch[kMaxDevices];
+
+static int scratch_on(int dev, unsigned char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return RSST_E_DEVICE;
+  unsigned char* p = g_scratch[dev].load(std::memory_order_acquire);
+  if (!p) {
+    void* q = nullptr;
+    if (hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)) != hipSuccess || !q) return RSST_E_DEVICE;
+    p = (unsigned char*)q;
+    g_scratch[dev].store(p, std::memory_order_release);
+  }
+  *out = p;
+  return RSST_OK;
+}
+
+// Zeroes the device scalars (a kernel, not a memset node, so a captured call
+// replays correctly).
+__global__ void __launch_bounds__(64) noalloc_clear_kernel(double* scal) {
+  if (threadIdx.x < rsstk::kNumScalars) scal[threadIdx.x] = 0.0;
+}
+
+// Copies the non-physical flags of the step into the caller's word.
+__global__ void __launch_bounds__(64) noalloc_flags_kernel(const double* scal, uint32_t* flags) {
+  if (threadIdx.x == 0) *flags = *(const uint32_t*)(scal + rsstk::kFlags);
+}
+
+static size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+extern "C" {
+
+const char* rsst_strerror(int s) {
+  switch (s) {
+    case RSST_OK: return "success";
+    case RSST_E_ARG: return "invalid argument or configuration";
+    case RSST_E_NOMEM: return "device allocation failed";
+    case RSST_E_DEVICE: return "HIP runtime call failed";
+    case RSST_E_UNSUPPORTED: return "configuration not supported by this build";
+    case RSST_E_NONPHYSICAL: return "non-physical state (rho <= 0, P <= 0 or non-finite)";
+    case RSST_E_SCRATCH: return "state too large for the fixed scratch of rsst_step_noalloc (64 MiB)";
+    default: return "unknown status";
+  }
+}
+
+const char* rsst_version(void) { return "rsst-gfx950 stage-v15"; }
+
+int rsst_init(const rsst_config* cfg, void* stream, rsst_handle* out) {
+  if (!out) return RSST_E_ARG;
+  *out = nullptr;
+  int st = validate(cfg);
+  if (st != RSST_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+
+  rsst_solver* h = new (std::nothrow) rsst_solver();
+  if (!h) return RSST_E_NOMEM;
+  h->cfg = *cfg;
+  h->nv = cfg->ndim + 2;
+  h->ncell = (long long)cfg->n[0] * cfg->n[1] * cfg->n[2];
+  h->elem = cfg->prec == RSST_FP32_PERT ? sizeof(float) : sizeof(double);
+  if (hipGetDevice(&h->device) != hipSuccess) { delete h; return RSST_E_DEVICE; }
+
+  StageArgs& a = h->args;
+  fill_args(cfg, h->ncell, a);
   h->npart = rsstk::diag_partials(h->ncell);
   const size_t ubytes = (size_t)h->nv * h->ncell * h->elem;
   if (hipMalloc(&h->u1, ubytes) != hipSuccess) { delete h; return RSST_E_NOMEM; }
   const size_t nscal = rsstk::kNumScalars;
-  a.nblk = a.geo.ntile_s * a.geo.nchunk;
-  a.big = (cfg->ndim == 3 && (long long)h->nv * h->ncell * (long long)h->elem >= (1ll << 31)) ? 1 : 0;
   h->scal = h->blkmax = h->part = h->diag_out = nullptr;
   if (hipMalloc((void**)&h->scal, nscal * sizeof(double)) != hipSuccess ||
       hipMalloc((void**)&h->blkmax, (size_t)a.nblk * sizeof(double)) != hipSuccess ||
@@ -370,4 +417,49 @@ int rsst_adjoint_step(rsst_handle h, const void* U, double* lam, double dt, doub
   return check(rsstk::launch_adjoint_step(p, (const double*)U, (const double*)h->u1, lam, dt, dJdxi, s));
 }
 
+int rsst_step_noalloc(const rsst_config* cfg, void* U, double dt_fixed, uint32_t* flags, void* stream) {
+  if (!U || !std::isfinite(dt_fixed)) return RSST_E_ARG;
+  int st = validate(cfg);
+  if (st != RSST_OK) return st;
+  if ((cfg->flags & RSST_WITH_ADJOINT) || cfg->t_end != 0.0) return RSST_E_UNSUPPORTED;
+  const long long ncell = (long long)cfg->n[0] * cfg->n[1] * cfg->n[2];
+  const size_t elem = cfg->prec == RSST_FP32_PERT ? sizeof(float) : sizeof(double);
+  StageArgs a;
+  fill_args(cfg, ncell, a);
+  // scratch layout: scalars | CFL maxima | U1, each 256-byte aligned
+  const size_t o_blk = round256(rsstk::kNumScalars * sizeof(double));
+  const size_t o_u1 = o_blk + round256((size_t)a.nblk * sizeof(double));
+  const size_t need = o_u1 + (size_t)(cfg->ndim + 2) * (size_t)ncell * elem;
+  if (need > kScratchBytes) return RSST_E_SCRATCH;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return RSST_E_DEVICE;
+  unsigned char* base = nullptr;
+  st = scratch_on(dev, &base);
+  if (st != RSST_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  a.scal = (double*)base;
+  a.blkmax = (double*)(base + o_blk);
+  void* u1 = base + o_u1;
+  a.dt_fixed = dt_fixed > 0.0 ? dt_fixed : 0.0;
+  hipLaunchKernelGGL(noalloc_clear_kernel, dim3(1), dim3(64), 0, s, a.scal);
+  if (hipGetLastError() != hipSuccess) return RSST_E_DEVICE;
+  // a CFL step: the maxima of U, t = 0
+  if (!(dt_fixed > 0.0) && rsstk::launch_prime(a, U, 0.0, 1, s) != hipSuccess) return RSST_E_DEVICE;
+  StageArgs a1 = a, a2 = a;
+  a1.uin = U;
+  a1.un = nullptr;
+  a1.uout = u1;
+  a2.uin = u1;
+  a2.un = U;
+  a2.uout = U;
+  if (rsstk::launch_stage(a1, 1, s) != hipSuccess || rsstk::launch_stage(a2, 2, s) != hipSuccess)
+    return RSST_E_DEVICE;
+  if (flags) {
+    hipLaunchKernelGGL(noalloc_flags_kernel, dim3(1), dim3(64), 0, s, (const double*)a.scal, flags);
+    if (hipGetLastError() != hipSuccess) return RSST_E_DEVICE;
+  }
+  return RSST_OK;
+}
+
 }  // extern "C"
+

@@ -39,7 +39,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_strerror_and_version():
     L = R.lib()
-    for code in (0, -1, -2, -3, -4, -5, 7):
+    for code in (0, -1, -2, -3, -4, -5, -6, 7):
         assert L.rsst_strerror(code)
     assert "gfx950" in R.rsst_version()
 
@@ -161,3 +161,27 @@ def test_null_arguments():
     assert L.rsst_destroy(None) == -1
     h = ctypes.c_void_p()
     assert L.rsst_init(None, None, ctypes.byref(h)) == -1
+
+
+def test_noalloc_step_checks_on_host():
+    """rsst_step_noalloc validates the configuration and the scratch size on
+    the host before any device call (the state pointer is never touched)."""
+    L = R.lib()
+    fake = ctypes.c_void_p(0x1000)
+    cfg, _ = W.random_state(2, [16, 12])
+    bad = R.make_config(dict(cfg, gamma=1.0))
+    assert L.rsst_step_noalloc(ctypes.byref(bad), fake, ctypes.c_double(0.0), None, None) == -1
+    ok = R.make_config(cfg)
+    assert L.rsst_step_noalloc(ctypes.byref(ok), None, ctypes.c_double(0.0), None, None) == -1
+    assert L.rsst_step_noalloc(None, fake, ctypes.c_double(0.0), None, None) == -1
+    assert L.rsst_step_noalloc(ctypes.byref(R.make_config(cfg, t_end=1.0)), fake,
+                               ctypes.c_double(0.0), None, None) == -4
+    assert L.rsst_step_noalloc(ctypes.byref(R.make_config(cfg, adjoint=True)), fake,
+                               ctypes.c_double(0.0), None, None) == -4
+    # 3D 128^3 FP64: 80 MiB of state, beyond the 64 MiB scratch
+    big, _ = W.random_state(3, [8, 8, 8])
+    c = R.make_config(big)
+    for d in range(3):
+        c.n[d] = 128
+    assert L.rsst_step_noalloc(ctypes.byref(c), fake, ctypes.c_double(0.0), None, None) == -6
+    assert b"scratch" in L.rsst_strerror(-6)
