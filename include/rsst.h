@@ -180,8 +180,11 @@ int rsst_get_time(rsst_handle h, double* t, double* dt_next, void* stream);
 
 /* FP64 diagnostics of U, summed over cells in a fixed order (deterministic):
  * out[0..7] = (sum rho, sum m1, sum m2, sum m3, sum E, sum |m|^2/(2 rho),
- *              max |V|, max xi |V| / a), sums times the cell volume.
- * Synchronises the stream. */
+ *              max |V|, max xi |V| / a), sums times the cell volume.  The
+ * sums are the conserved totals of Sec. 5 (which forms conserve mass,
+ * momentum or energy) and the kinetic energy; max xi |V| / a is the
+ * effective Mach number whose bound Sec. 4.3 discusses (with C_max, xi of
+ * each cell's own sound speed, eq. cx).  Synchronises the stream. */
 int rsst_diag(rsst_handle h, const void* U, double out[8], void* stream);
 
 /* Synchronises, copies the non-physical flags seen since the last poll into

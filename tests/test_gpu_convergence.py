@@ -1,10 +1,11 @@
 """Sec. 4.2 on the GPU: the linear entropy + shear wave at 30 degrees, xi = 5,
 run to t = 1 (one period) with the CFL step cut at t_end.
 
-Parity: at N = 16 and 32 the GPU state at t = 1 matches the oracle's within
-the FP64 bar of the other parity tests (or, where this run's own rounding
-sensitivity is larger, ten times the oracle's spread under a last-bit
-change of the input), in every form.  Convergence: the L1
+Parity: at N = 16 and 32 the first 25 steps match the oracle within the
+FP64 bar of the other parity tests, and the state at t = 1 within that bar
+or, where this run's own rounding sensitivity is larger, ten times the
+oracle's largest spread under eight independent last-bit changes of the
+input, in every form.  Convergence: the L1
 errors against the initial snapshot at N = 64, 128, 256 (average order over
 the two doublings) follow what the paper states: S and V_perp at second order in every form, rho and P at
 second order in PVS, PMS and PD, and P not converging in DVS and DMS."""
@@ -56,34 +57,68 @@ def _l1(U0, U1, th):
     return {k: float(np.mean(np.abs(f1[k] - f0[k]))) for k in f0}
 
 
+NDRAW = 8
+
+
+def _spread_runs(cfg, U0, nsteps, t_end, draws, seed_k):
+    """The oracle from `draws` independent last-bit changes of the input
+    (each value times 1 +- 2^-52, signs drawn independently per draw)."""
+    rng = np.random.default_rng(W.seed(seed_k))
+    return [oracle.run(cfg, U0 * (1 + 2.2e-16 * rng.choice([-1.0, 1.0], size=U0.shape)), nsteps,
+                       t_end=t_end)[0] for _ in range(draws)]
+
+
 @pytest.mark.parametrize("form", FORMS)
 def test_wave_matches_oracle_small_grids(form):
-    """The bar is 1e-12 of the natural scales, or ten times the oracle's own
-    spread where that is larger: in the P-forms this run amplifies a
-    last-bit change of the input (2.2e-16) to ~1e-10 of the natural scales
-    by t = 1, so two correct FP64 codes that round differently cannot agree
-    better than that.  The spread is measured here, on the same run."""
-    rng = np.random.default_rng(W.seed(80))
+    """The first 25 steps at 1e-12 of the natural scales.  To t = 1 the bar
+    is 1e-12, or ten times the oracle's own spread where that is larger: in
+    the P-forms this run amplifies a last-bit change of the input (2.2e-16)
+    to ~1e-10 of the natural scales by t = 1, so two correct FP64 codes that
+    round differently cannot agree better than that.  The spread is the
+    largest over eight independent last-bit changes, on the same run.  (The
+    oracle's own spread is 1e-14 to 7e-14 after 25 steps, 1e-13 to 4e-13
+    after 50 and 1e-11 to 8e-11 after 100 in the P-forms, measured with the
+    same draws, so 25 steps is where 1e-12 still has a decade of margin.)"""
     for N in (16, 32):
+        cfg, U0, meta = W.wave2d_oblique(N, form)
+        U = torch.from_numpy(U0).cuda()
+        s = R.Solver(cfg, t_end=meta["t_end"])
+        s.steps(U, 25)
+        torch.cuda.synchronize()
+        t100, _ = s.time()
+        s.close()
+        Ug100 = U.cpu().numpy()
+        Uo100, to100, _ = oracle.run(cfg, U0, 25, t_end=1.0)
+        assert t100 == pytest.approx(to100, rel=1e-13)
+        s100 = _scales(Uo100)
+        e100 = [float(np.abs(Ug100[v] - Uo100[v]).max() / s100[v]) for v in range(4)]
+        print(f"[wave] {form} N={N} first 25 steps err/scale={max(e100):.2e}", flush=True)
+        assert max(e100) <= 1e-12, e100
+
         cfg, U0, Ug, t, th = _gpu_run(N, form)
         assert t == 1.0
         Uo, to, _ = oracle.run(cfg, U0, 10 ** 6, t_end=1.0)
         assert to == 1.0
-        Up, _, _ = oracle.run(cfg, U0 * (1 + 2.2e-16 * rng.choice([-1.0, 1.0], size=U0.shape)), 10 ** 6,
-                              t_end=1.0)
-        rho = Uo[0]
-        P = (GAMMA - 1) * (Uo[3] - 0.5 * (Uo[1] ** 2 + Uo[2] ** 2) / rho)
-        sm = np.abs(rho).max() * np.sqrt(GAMMA * P / rho).max()
-        s = [np.abs(rho).max(), sm, sm, np.abs(Uo[3]).max()]
-        err = [float(np.abs(Ug[v] - Uo[v]).max() / s[v]) for v in range(4)]
-        spread = [float(np.abs(Up[v] - Uo[v]).max() / s[v]) for v in range(4)]
-        eg, eo, ep = _l1(U0, Ug, th), _l1(U0, Uo, th), _l1(U0, Up, th)
-        print(f"[wave] {form} N={N} err/scale={max(err):.2e} oracle spread={max(spread):.2e} "
-              f"L1 gpu {eg} oracle {eo}", flush=True)
+        Ups = _spread_runs(cfg, U0, 10 ** 6, 1.0, NDRAW, 80 + N)
+        sc = _scales(Uo)
+        err = [float(np.abs(Ug[v] - Uo[v]).max() / sc[v]) for v in range(4)]
+        spread = [max(float(np.abs(Up[v] - Uo[v]).max() / sc[v]) for Up in Ups) for v in range(4)]
+        eg, eo = _l1(U0, Ug, th), _l1(U0, Uo, th)
+        ep = [_l1(U0, Up, th) for Up in Ups]
+        print(f"[wave] {form} N={N} err/scale={max(err):.2e} oracle spread (max of {NDRAW})="
+              f"{max(spread):.2e} L1 gpu {eg} oracle {eo}", flush=True)
         for v in range(4):
             assert err[v] <= max(1e-12, 10 * spread[v]), (v, err[v], spread[v])
         for k in eg:
-            assert abs(eg[k] - eo[k]) <= 1e-3 * eo[k] + 10 * abs(ep[k] - eo[k]), (k, eg[k], eo[k], ep[k])
+            dk = max(abs(e[k] - eo[k]) for e in ep)
+            assert abs(eg[k] - eo[k]) <= 1e-3 * eo[k] + 10 * dk, (k, eg[k], eo[k], dk)
+
+
+def _scales(Uo):
+    rho = Uo[0]
+    P = (GAMMA - 1) * (Uo[3] - 0.5 * (Uo[1] ** 2 + Uo[2] ** 2) / rho)
+    sm = np.abs(rho).max() * np.sqrt(GAMMA * P / rho).max()
+    return [np.abs(rho).max(), sm, sm, np.abs(Uo[3]).max()]
 
 
 @pytest.mark.parametrize("form", FORMS)

@@ -214,6 +214,36 @@ def test_fp32_perturbation_matches_fp64_oracle_2d_uniform_bg():
     assert max(err) <= 1e-5, err
 
 
+@pytest.mark.parametrize("ndim,n,axis,wall", [
+    (3, [40, 12, 9], 0, None),        # background along x (per-lane profile)
+    (3, [36, 22, 7], 1, None),        # along y: the stacked rows' own profile rows
+    (3, [70, 9, 14], 1, "reflect"),   # along y, walls on every axis
+    (2, [48, 30], 0, "reflect"),      # along x, with y walls
+    (1, [90], 0, None),               # along the only axis
+])
+def test_fp32_perturbation_background_on_any_axis(ndim, n, axis, wall):
+    """FP32 perturbation about a background that varies along x or y (the
+    stratified box turned so that gravity and the walls lie on that axis),
+    20 steps against the FP64 oracle run from U0 + U1(0), at 1e-5 of the
+    perturbation."""
+    cfg, U0, meta = W.stratified(ndim, n, axis, xi=20.0, seed_k=40 + axis + 3 * ndim, wall_bc=wall)
+    bg = meta["bg"]
+    bshape = [U0.shape[0]] + [1] * ndim
+    bshape[ndim - axis] = n[axis]
+    bgb = bg.reshape(bshape)
+    U1 = (U0 - bgb).astype(np.float32)
+    Ustart = bgb + U1.astype(np.float64)
+    nsteps = 20
+    print(f"[fp32 bg] {ndim}D n={n} bg_axis={axis} walls={wall}", flush=True)
+    Ug, tg, _, flags = gpu_run(cfg, U1, nsteps, prec="fp32_pert", bg=bg, bg_axis=axis)
+    Uo, to, _ = oracle.run(cfg, Ustart, nsteps)
+    assert flags == 0
+    assert abs(tg - to) <= 1e-6 * to
+    err = pert_errors(Ug, Uo, bgb, ndim)
+    print(f"[fp32 bg] err/|pert| per var = {['%.2e' % e for e in err]}", flush=True)
+    assert max(err) <= 1e-5, err
+
+
 # ------------------------------------------------------------ invariants
 
 def test_uniform_state_bitwise_3d():

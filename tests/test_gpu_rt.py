@@ -1,10 +1,11 @@
 """Sec. 4.4 Rayleigh-Taylor problem on the GPU (gravity, closed walls, large
 hydrostatic pressure, the xi-fold longer time step).
 
-Parity: at 64^2 the GPU state after 150 CFL steps matches the oracle's in
-the PVS and PMS forms at xi = 6.3 and at xi = 1 (the bar of the other FP64
-tests, or ten times the oracle's own spread under a last-bit change of the
-input where this run amplifies rounding more).  Step saving: at 128^2 to
+Parity: at 64^2 the GPU state after 100 CFL steps matches the oracle's at
+1e-12 of the natural scales, and after 150 within that bar or ten times the
+oracle's largest spread under eight independent last-bit changes of the
+input where this run amplifies rounding more, in the PVS and PMS forms at
+xi = 6.3 and at xi = 1.  Step saving: at 128^2 to
 t = 0.5 the RSST run at xi = 6.3 takes at least 4x fewer steps than xi = 1
 (c_tot is dominated by the sound speed, so the ratio approaches xi), and the
 growth of max |V_y| agrees with the xi = 1 run to 10% (the paper's
@@ -39,24 +40,34 @@ def _scales(Uo):
 
 @pytest.mark.parametrize("form,xi", [("pvs", 6.3), ("pms", 6.3), ("pvs", 1.0)])
 def test_rt_matches_oracle(form, xi):
+    """100 steps at 1e-12 of the natural scales; 150 steps within 1e-12 or
+    ten times the oracle's largest spread over eight independent last-bit
+    changes of the input, where this run amplifies rounding more."""
     cfg, U0, _ = W.rt2d(64, form=form, xi=xi)
-    nsteps = 150
-    U = torch.from_numpy(U0).cuda()
-    s = R.Solver(cfg)
-    s.steps(U, nsteps)
-    tg, _ = s.time()
-    s.close()
-    Ug = U.cpu().numpy()
-    Uo, to, _ = oracle.run(cfg, U0, nsteps)
-    rng = np.random.default_rng(W.seed(81))
-    Up, _, _ = oracle.run(cfg, U0 * (1 + 2.2e-16 * rng.choice([-1.0, 1.0], size=U0.shape)), nsteps)
-    sc = _scales(Uo)
-    err = [float(np.abs(Ug[v] - Uo[v]).max() / sc[v]) for v in range(4)]
-    spread = [float(np.abs(Up[v] - Uo[v]).max() / sc[v]) for v in range(4)]
-    print(f"[rt] {form} xi={xi} err/scale={err} spread={spread} t={tg}/{to}", flush=True)
-    for v in range(4):
-        assert err[v] <= max(1e-12, 10 * spread[v]), (v, err[v], spread[v])
-    assert abs(tg - to) <= 1e-12 * to
+    for nsteps in (100, 150):
+        U = torch.from_numpy(U0).cuda()
+        s = R.Solver(cfg)
+        s.steps(U, nsteps)
+        tg, _ = s.time()
+        s.close()
+        Ug = U.cpu().numpy()
+        Uo, to, _ = oracle.run(cfg, U0, nsteps)
+        sc = _scales(Uo)
+        err = [float(np.abs(Ug[v] - Uo[v]).max() / sc[v]) for v in range(4)]
+        assert abs(tg - to) <= 1e-12 * to
+        if nsteps == 100:
+            print(f"[rt] {form} xi={xi} 100 steps err/scale={err}", flush=True)
+            assert max(err) <= 1e-12, err
+            continue
+        rng = np.random.default_rng(W.seed(81))
+        spread = [0.0] * 4
+        for _ in range(8):
+            Up, _, _ = oracle.run(cfg, U0 * (1 + 2.2e-16 * rng.choice([-1.0, 1.0], size=U0.shape)), nsteps)
+            spread = [max(spread[v], float(np.abs(Up[v] - Uo[v]).max() / sc[v])) for v in range(4)]
+        print(f"[rt] {form} xi={xi} 150 steps err/scale={err} spread (max of 8)={spread} t={tg}/{to}",
+              flush=True)
+        for v in range(4):
+            assert err[v] <= max(1e-12, 10 * spread[v]), (v, err[v], spread[v])
 
 
 def run_to(s, U, t_end):

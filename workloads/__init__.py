@@ -200,6 +200,31 @@ def strat3d(n=256, xi=30.0, form="pvs", nz=None, ny=None, gas=None):
     return cfg, U, {"bg": bg, "bg_axis": 2}
 
 
+def stratified(ndim, n, axis, *, xi=30.0, form="pvs", contrast=100.0, seed_k=30, wall_bc=None):
+    """A polytrope (as strat3d) along any axis: gravity 1 along -axis, walls
+    on that axis, periodic on the others (or wall_bc on the others), V = 0,
+    pressure noise 1e-3 relative.  Background: the unperturbed profile
+    [nv][n[axis]]."""
+    bc = [wall_bc or "periodic"] * ndim
+    bc[axis] = "reflect"
+    g = [0.0] * ndim
+    g[axis] = -1.0
+    cfg = base_cfg(ndim, n, xi=xi, form=form, bc_lo=bc, g=g)
+    z = centres(cfg, axis)
+    rho0, P0 = polytrope(z, contrast=contrast)
+    shape = tuple(reversed(list(n)[:ndim]))  # [nz][ny][nx] order
+    bshape = [1] * ndim
+    bshape[ndim - 1 - axis] = n[axis]
+    rng = np.random.default_rng(seed(seed_k))
+    noise = rng.uniform(-1.0, 1.0, size=shape)
+    rho = np.broadcast_to(rho0.reshape(bshape), shape)
+    P = P0.reshape(bshape) * (1.0 + 1e-3 * noise)
+    zero = np.zeros(shape)
+    U = conservative(rho, [zero] * ndim, P)
+    bg = conservative(rho0, [np.zeros(n[axis])] * ndim, P0)
+    return cfg, U, {"bg": bg, "bg_axis": axis}
+
+
 def strat2d_box(n, contrast, xi, rng, form="pvs"):
     """One 2D stratified box: polytrope along -y, walls in y, periodic in x."""
     cfg = base_cfg(2, [n, n], xi=xi, form=form, bc_lo=["periodic", "reflect"],
