@@ -32,7 +32,7 @@
 //     halo rows) run on the same XCD and share its L2.
 #include <cstdlib>
 
-#include "rsst_stage.h"
+#include "rsst_stage3.h"
 
 #pragma clang fp contract(off)
 
@@ -190,7 +190,8 @@ Geometry plan_geometry(int ndim, const int n[3]) {
     // 3D rows of 5-8 waves run as rows of 8 (the waves past the row's end
     // compute on clamped cells and store nothing)
     if (G.nwx > 4) G.nwx = 8;
-    G.ts = tile_rows(G.nwx);
+    // an even number of rows (two per thread), at most the grid's (>= 4)
+    G.ts = tile_rows3(G.nwx) < (G.ns & ~1) ? tile_rows3(G.nwx) : (G.ns & ~1);
   } else {
     G.ts = 1;
   }
@@ -218,8 +219,8 @@ Geometry plan_geometry(int ndim, const int n[3]) {
     G.km = km < G.nm ? km : G.nm;
   }
   G.nchunk = (G.nm + G.km - 1) / G.km;
-  G.threads = 64 * G.nwx * G.ts;
-  G.lds_bytes = (size_t)carve(ndim, G.ts, G.nwx).total * sizeof(double);
+  G.threads = 64 * G.nwx * (ndim == 3 ? G.ts / 2 : G.ts);
+  G.lds_bytes = (size_t)(ndim == 3 ? carve3(G.ts, G.nwx).total : carve(ndim, G.ts, G.nwx).total) * sizeof(double);
   return G;
 }
 

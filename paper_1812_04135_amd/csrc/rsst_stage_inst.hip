@@ -3,7 +3,7 @@
 // Compiled once per (RSST_INST_NDIM, RSST_INST_ST, RSST_INST_BIG) so the
 // library builds in parallel objects; RSST_INST_BIG = 1 builds the 3D
 // kernels that address states of 2 GiB or more (Field64).
-#include "rsst_stage.h"
+#include "rsst_stage3.h"
 
 #pragma clang fp contract(off)
 
@@ -34,22 +34,24 @@ __global__ void __launch_bounds__(NDIM == 3 ? kMaxThreads3 : 1024) stage_kernel(
   const int L = xcd_tile(blockIdx.x, gridDim.x);
   const int tile_s = L % G.ntile_s;
   const int chunk_base = (L / G.ntile_s) * (NDIM == 3 ? 1 : G.ts);
-  const Carve C = carve(NDIM, NDIM == 3 ? tile_rows(NWXC) : G.ts, NDIM == 3 ? NWXC : G.nwx);
+  const int red = NDIM == 3 ? carve3(G.ts, NWXC).red : carve(NDIM, G.ts, G.nwx).red;
   // a CFL step's dt: formed by stage 1 from the maxima of the state it
   // reads, recorded for stage 2
   double dt = A.dt_fixed;
   if (!(A.dt_fixed > 0.0)) {
     if constexpr (STAGE == 1) {
-      dt = cfl_dt_from_blocks(A, lds + C.red);
+      dt = cfl_dt_from_blocks(A, lds + red);
       if (blockIdx.x == 0 && threadIdx.x == 0) A.scal[kDtCur] = dt;
     } else {
       dt = A.scal[kDtCur];
     }
   }
   unsigned bad = 0;
-  const double cmax = stage_body<NDIM, STAGE, ST, FORM, NWXC, BIG>(A, lds, tile_s, chunk_base, dt, bad);
+  double cmax;
+  if constexpr (NDIM == 3) cmax = stage_body3<STAGE, ST, FORM, NWXC, BIG>(A, lds, tile_s, chunk_base, dt, bad);
+  else cmax = stage_body<NDIM, STAGE, ST, FORM, NWXC, BIG>(A, lds, tile_s, chunk_base, dt, bad);
   if (bad) atomicOr((unsigned*)(A.scal + kFlags), bad);
-  if constexpr (STAGE == 2) cfl_epilogue(A, lds + C.red, cmax, dt);
+  if constexpr (STAGE == 2) cfl_epilogue(A, lds + red, cmax, dt);
 }
 
 template <int NDIM, int STAGE, typename ST, int FORM, int NWXC>
