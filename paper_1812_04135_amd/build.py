@@ -24,8 +24,9 @@ HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile each source to an object in _build/ (in parallel), then link."""
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile each source to an object in _build/ (in parallel), then link.
+    incremental: keep objects newer than every source and header."""
     from concurrent.futures import ThreadPoolExecutor
 
     objdir = os.path.join(HERE, "_build")
@@ -44,12 +45,19 @@ def build(verbose: bool = False) -> str:
         objs.append(obj)
         cmds.append(["hipcc"] + compile_flags + inc + ["-c", os.path.join(HERE, src), "-o", obj])
 
+    if incremental:
+        hdr = max(os.path.getmtime(os.path.join(d, f)) for d in (os.path.join(HERE, "csrc"), os.path.join(ROOT, "include"))
+                  for f in os.listdir(d) if f.endswith(".h"))
+        stale = lambda c, o: (not os.path.exists(o) or
+                              os.path.getmtime(o) < max(hdr, os.path.getmtime(os.path.join(HERE, c[-3]))))
+        cmds = [c for c, o in zip(cmds, objs) if stale(c, o)]
+
     def run(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True, cwd=HERE)
 
-    with ThreadPoolExecutor(max_workers=min(len(cmds), max(1, os.cpu_count() or 1))) as ex:
+    with ThreadPoolExecutor(max_workers=max(1, min(len(cmds), os.cpu_count() or 1))) as ex:
         list(ex.map(run, cmds))
     tmp = LIB + ".tmp"
     run(["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp])

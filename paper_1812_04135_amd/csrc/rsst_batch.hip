@@ -28,7 +28,7 @@
 #include <vector>
 
 #include "rsst.h"
-#include "rsst_stage.h"
+#include "rsst_stage2.h"
 
 #pragma clang fp contract(off)
 
@@ -208,9 +208,9 @@ __global__ void __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per
     if (skip_item) {
       // nothing computed or stored; the item is still signalled done below
     } else if (!st2) {
-      cmax = stage_body<2, 1, ST, FORM, 0>(B.s1, lds, 0, p * B.groups, dt, bad);
+      cmax = stage_body2<1, ST, FORM>(B.s1, lds, p * B.groups, dt, bad);
     } else {
-      cmax = stage_body<2, 2, ST, FORM, 0>(B.s2, lds, 0, p * B.groups, dt, bad);
+      cmax = stage_body2<2, ST, FORM>(B.s2, lds, p * B.groups, dt, bad);
     }
     if (bad) atomicOr(S.flags, bad);
     if (st2) {
@@ -369,7 +369,7 @@ static int batch_build(rsst_batch_s* h, void* U) {
     G.ntile_s = 1;
     G.nchunk = (G.nm + G.km - 1) / G.km;
     G.threads = kBatchThreads;
-    G.lds_bytes = (size_t)carve(2, groups, G.nwx).total * sizeof(double);
+    G.lds_bytes = (size_t)carve2(groups, G.nwx).total * sizeof(double);
     if (G.lds_bytes > lds) lds = G.lds_bytes;
     a.ncell = (long long)G.nx * G.nm;
     for (int d = 0; d < 3; ++d) {

@@ -32,6 +32,7 @@
 //     halo rows) run on the same XCD and share its L2.
 #include <cstdlib>
 
+#include "rsst_stage2.h"
 #include "rsst_stage3.h"
 
 #pragma clang fp contract(off)
@@ -220,7 +221,9 @@ Geometry plan_geometry(int ndim, const int n[3]) {
   }
   G.nchunk = (G.nm + G.km - 1) / G.km;
   G.threads = 64 * G.nwx * (ndim == 3 ? G.ts / 2 : G.ts);
-  G.lds_bytes = (size_t)(ndim == 3 ? carve3(G.ts, G.nwx).total : carve(ndim, G.ts, G.nwx).total) * sizeof(double);
+  G.lds_bytes = (size_t)(ndim == 3 ? carve3(G.ts, G.nwx).total
+                                    : (ndim == 2 ? carve2(G.ts, G.nwx).total : carve(ndim, G.ts, G.nwx).total)) *
+                sizeof(double);
   return G;
 }
 

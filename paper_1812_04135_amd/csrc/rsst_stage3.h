@@ -109,21 +109,39 @@ __device__ __forceinline__ double stage_body3(const StageArgs& A, double* lds, i
   double* const xs = FXS + rl * (NV * NWXC) + wx;   // + c NV NWXC + v NWXC
 
   // FP32 perturbation form: the background in registers.  Along z: bgA holds
-  // plane k for both cells and bgB plane k + 2, loaded at the top of each
-  // plane; otherwise (uniform, along x, along y) bgA holds the lower cell's
-  // values and bgH the upper cell's for the whole march.  Rows outside the
-  // tile with a profile along y take the indexed path.
+  // plane k and bgB plane k + 2, loaded at the top of each plane; otherwise
+  // (uniform, along x, along y) bgA holds the lower cell's values for the
+  // whole march.  With a profile along y the upper cell and the rows outside
+  // the tile take the indexed path (loads where used).
   const bool bg_on_m = F32 && A.bg_axis == 2;
   const bool bg_rows = F32 && A.bg_axis == 1;
   auto bg_cell = [&](int c) { return A.bg_axis == 0 ? i : (A.bg_axis == 1 ? jl + c : 0); };
-  double bgA[NV], bgH[NV], bgB[NV];
+  double bgA[NV], bgB[NV];
   const __amdgpu_buffer_rsrc_t bgr = field_rsrc(A.bg, F32 ? (long long)NV * A.nbg * 8 : 0);
   if constexpr (F32) {
-    if (!bg_on_m) {
-      load_bg<NV>(bgr, A.nbg, A.bg_uniform ? 0 : bg_cell(0), bgA);
-      load_bg<NV>(bgr, A.nbg, A.bg_uniform ? 0 : bg_cell(1), bgH);
-    }
+    if (!bg_on_m) load_bg<NV>(bgr, A.nbg, A.bg_uniform ? 0 : bg_cell(0), bgA);
   }
+  // FP64 state of stored values: FP32, with the background at profile index b
+  // (vector loads where used); FP64, with the mirror sign and the hydrostatic
+  // wall's carried pressure (lever)
+  auto fin_idx = [&](const ST (&raw)[NV], int neg, int b, double lev, double (&u)[NV]) {
+    if constexpr (F32) {
+      double bz[NV];
+      load_bg<NV>(bgr, A.nbg, b, bz);
+      finish_cell_bgv<NDIM, ST>(raw, neg, bz, u);
+    } else {
+      finish_cell<NDIM, ST>(A, raw, neg, 0, u, lev);
+    }
+  };
+  // FP32: cell c's stored values at plane k with the background bgz (of plane
+  // k, or of the plane two ahead for the march loads); a profile along y
+  // takes the upper cell's own row
+  auto fin_c = [&](const ST (&raw)[NV], int neg, int c, const double (&bgz)[NV], double (&u)[NV]) {
+    if constexpr (F32) {
+      if (c == 1 && bg_rows) fin_idx(raw, neg, jl + 1, 0.0, u);
+      else finish_cell_bgv<NDIM, ST>(raw, neg, bgz, u);
+    }
+  };
 
   const Consts K{A.gamma, A.gm1, A.inv_gm1, A.inv_xi, A.f, A.inv_cmax2, A.vdw_a, A.vdw_b};
   const double g[3] = {A.g[0], A.g[1], A.g[2]};
@@ -174,9 +192,9 @@ __device__ __forceinline__ double stage_body3(const StageArgs& A, double* lds, i
   const double ol1 = o_lo ? llo1 : lhi1, ol2 = o_lo ? llo2 : lhi2;
   ST o1[NV], o2[NV], o3[ONE ? NV : 1], o4[ONE ? NV : 1];  // stored values, finished at use
   // an outside row's FP64 state at plane k
-  auto fin_out = [&](const ST (&raw)[NV], int neg, int b, double lev, int k, double (&u)[NV]) {
+  auto fin_out = [&](const ST (&raw)[NV], int neg, int b, double lev, double (&u)[NV]) {
     if (F32 && !bg_rows) finish_cell_bgv<NDIM, ST>(raw, neg, bgA, u);
-    else finish_cell<NDIM, ST>(A, raw, neg, bg_on_m ? k : b, u, lev);
+    else fin_idx(raw, neg, b, lev, u);
   };
 
   double q0[2][NV], q1[2][NV], sm0[2][NV], Fm_lo[2][NV];
@@ -188,17 +206,17 @@ __device__ __forceinline__ double stage_body3(const StageArgs& A, double* lds, i
     bool n;
     int kk;
     const int b = A.bg_uniform ? 0 : bg_cell(c);
-    auto bgk = [&](int q) { return bg_on_m ? q : b; };
-    kk = map_index(k0l - 2, G.nm, rm_lo, rm_hi, n);
-    load_cell<NDIM, ST>(A, uin, kk, colc[c], n ? NDIM : -1, bgk(kk), qa,
-                        HYD ? hydro_lever(k0l - 2, G.nm, rm_lo, rm_hi, A.dx[2], A.g[2]) : 0.0);
-    kk = map_index(k0l - 1, G.nm, rm_lo, rm_hi, n);
-    load_cell<NDIM, ST>(A, uin, kk, colc[c], n ? NDIM : -1, bgk(kk), qb,
-                        HYD ? hydro_lever(k0l - 1, G.nm, rm_lo, rm_hi, A.dx[2], A.g[2]) : 0.0);
-    load_cell<NDIM, ST>(A, uin, k0l, colc[c], -1, bgk(k0l), q0[c]);
-    kk = map_index(k0l + 1, G.nm, rm_lo, rm_hi, n);
-    load_cell<NDIM, ST>(A, uin, kk, colc[c], n ? NDIM : -1, bgk(kk), q1[c],
-                        HYD ? hydro_lever(k0l + 1, G.nm, rm_lo, rm_hi, A.dx[2], A.g[2]) : 0.0);
+    auto ld = [&](int q, double (&u)[NV]) {  // plane k0l + q of the cell's column, through the z walls
+      const int kk = map_index(k0l + q, G.nm, rm_lo, rm_hi, n);
+      ST raw[NV];
+      load_cell_raw<NDIM, ST>(uin, kk, colc[c], raw);
+      fin_idx(raw, n ? NDIM : -1, bg_on_m ? kk : b,
+              HYD ? hydro_lever(k0l + q, G.nm, rm_lo, rm_hi, A.dx[2], A.g[2]) : 0.0, u);
+    };
+    ld(-2, qa);
+    ld(-1, qb);
+    ld(0, q0[c]);
+    ld(1, q1[c]);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       ha[v] = mc_half(qb[v] - qa[v], q0[c][v] - qb[v]);
@@ -235,12 +253,6 @@ __device__ __forceinline__ double stage_body3(const StageArgs& A, double* lds, i
     }
 #pragma unroll
     for (int c = 0; c < 2; ++c) load_cell_raw<NDIM, ST>(uin, q2k, colc[c], q2r[c]);
-    if constexpr (F32) {
-      if (bg_on_m) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) bgH[v] = bgA[v];
-      }
-    }
 
     // ---- P1: publish both rows' cell states, and the x ghosts
 #pragma unroll
@@ -277,14 +289,14 @@ __device__ __forceinline__ double stage_body3(const StageArgs& A, double* lds, i
     {
       double uD[NV], uU[NV], d[NV], hh[NV];
       if (first) {
-        fin_out(o1, on1, ob1, ol1, k, uD);
+        fin_out(o1, on1, bg_on_m ? k : ob1, ol1, uD);
       } else {
 #pragma unroll
         for (int v = 0; v < NV; ++v) uD[v] = ub[v * PX + 1 - UR];
       }
       if (last) {
-        if constexpr (ONE) fin_out(o3, nhi1, bhi1, lhi1, k, uU);
-        else fin_out(o1, on1, ob1, ol1, k, uU);
+        if constexpr (ONE) fin_out(o3, nhi1, bg_on_m ? k : bhi1, lhi1, uU);
+        else fin_out(o1, on1, bg_on_m ? k : ob1, ol1, uU);
       } else {
 #pragma unroll
         for (int v = 0; v < NV; ++v) uU[v] = ub[2 * UR + v * PX + 1];
@@ -308,8 +320,8 @@ __device__ __forceinline__ double stage_body3(const StageArgs& A, double* lds, i
         // minus state of the row above the tile, and the flux at the
         // tile's upper face
         double u2[NV], h2[NV];
-        if constexpr (ONE) fin_out(o4, nhi2, bhi2, lhi2, k, u2);
-        else fin_out(o2, on2, ob2, ol2, k, u2);
+        if constexpr (ONE) fin_out(o4, nhi2, bg_on_m ? k : bhi2, lhi2, u2);
+        else fin_out(o2, on2, bg_on_m ? k : ob2, ol2, u2);
 #pragma unroll
         for (int v = 0; v < NV; ++v) h2[v] = mc_half(uU[v] - q0[1][v], u2[v] - uU[v]);
         Face<NV> fh;
@@ -320,7 +332,7 @@ __device__ __forceinline__ double stage_body3(const StageArgs& A, double* lds, i
         // plus state of the row below the tile, and the flux at the tile's
         // lower face
         double u2[NV], h2[NV];
-        fin_out(o2, on2, ob2, ol2, k, u2);
+        fin_out(o2, on2, bg_on_m ? k : ob2, ol2, u2);
 #pragma unroll
         for (int v = 0; v < NV; ++v) h2[v] = mc_half(uD[v] - u2[v], q0[0][v] - uD[v]);
         Face<NV> fh, fm;
@@ -399,11 +411,10 @@ __device__ __forceinline__ double stage_body3(const StageArgs& A, double* lds, i
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       if constexpr (F32) {
-        if (bg_on_m) finish_cell_bgv<NDIM, ST>(q2r[c], q2neg, bgB, q2[c]);
-        else if (c == 1) finish_cell_bgv<NDIM, ST>(q2r[c], q2neg, bgH, q2[c]);
-        else finish_cell_bgv<NDIM, ST>(q2r[c], q2neg, bgA, q2[c]);
+        if (bg_on_m) fin_c(q2r[c], q2neg, c, bgB, q2[c]);
+        else fin_c(q2r[c], q2neg, c, bgA, q2[c]);
       } else {
-        finish_cell<NDIM, ST>(A, q2r[c], q2neg, 0, q2[c], q2lev);
+        fin_idx(q2r[c], q2neg, 0, q2lev, q2[c]);
       }
       double sm1[NV], Fm_hi[NV];
 #pragma unroll
@@ -423,21 +434,25 @@ __device__ __forceinline__ double stage_body3(const StageArgs& A, double* lds, i
       double un[NV];
       if constexpr (STAGE == 2) {
         if constexpr (F32) {
-          if (c == 1) finish_cell_bgv<NDIM, ST>(unr[c], -1, bgH, un);
-          else finish_cell_bgv<NDIM, ST>(unr[c], -1, bgA, un);
+          fin_c(unr[c], -1, c, bgA, un);
         } else {
-          finish_cell<NDIM, ST>(A, unr[c], -1, 0, un);
+          fin_idx(unr[c], -1, 0, 0.0, un);
         }
       }
       if ((c == 0 ? own_lo : own_hi) && kval) {
         bad |= b;
-        double out[NV];
+        double out[NV], bgc[NV];
+        if constexpr (F32) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) bgc[v] = bgA[v];
+          if (c == 1 && bg_rows) load_bg<NV>(bgr, A.nbg, jl + 1, bgc);
+        }
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           double y = fma(dt, Rt[v], q0[c][v]);
           if constexpr (STAGE == 2) y = 0.5 * (un[v] + y);
           double bgv = 0.0;
-          if constexpr (F32) bgv = c == 1 ? bgH[v] : bgA[v];
+          if constexpr (F32) bgv = bgc[v];
           const ST st = (ST)(y - bgv);
           buf_store<ST, kStoreAux3>(uout.rsrc(v, k), colc[c], uout.soff(v, k), st);
           out[v] = (double)st + bgv;

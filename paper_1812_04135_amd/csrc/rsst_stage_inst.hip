@@ -3,6 +3,7 @@
 // Compiled once per (RSST_INST_NDIM, RSST_INST_ST, RSST_INST_BIG) so the
 // library builds in parallel objects; RSST_INST_BIG = 1 builds the 3D
 // kernels that address states of 2 GiB or more (Field64).
+#include "rsst_stage2.h"
 #include "rsst_stage3.h"
 
 #pragma clang fp contract(off)
@@ -34,7 +35,7 @@ __global__ void __launch_bounds__(NDIM == 3 ? kMaxThreads3 : 1024) stage_kernel(
   const int L = xcd_tile(blockIdx.x, gridDim.x);
   const int tile_s = L % G.ntile_s;
   const int chunk_base = (L / G.ntile_s) * (NDIM == 3 ? 1 : G.ts);
-  const int red = NDIM == 3 ? carve3(G.ts, NWXC).red : carve(NDIM, G.ts, G.nwx).red;
+  const int red = NDIM == 3 ? carve3(G.ts, NWXC).red : (NDIM == 2 ? carve2(G.ts, G.nwx).red : carve(NDIM, G.ts, G.nwx).red);
   // a CFL step's dt: formed by stage 1 from the maxima of the state it
   // reads, recorded for stage 2
   double dt = A.dt_fixed;
@@ -49,6 +50,7 @@ __global__ void __launch_bounds__(NDIM == 3 ? kMaxThreads3 : 1024) stage_kernel(
   unsigned bad = 0;
   double cmax;
   if constexpr (NDIM == 3) cmax = stage_body3<STAGE, ST, FORM, NWXC, BIG>(A, lds, tile_s, chunk_base, dt, bad);
+  else if constexpr (NDIM == 2) cmax = stage_body2<STAGE, ST, FORM>(A, lds, chunk_base, dt, bad);
   else cmax = stage_body<NDIM, STAGE, ST, FORM, NWXC, BIG>(A, lds, tile_s, chunk_base, dt, bad);
   if (bad) atomicOr((unsigned*)(A.scal + kFlags), bad);
   if constexpr (STAGE == 2) cfl_epilogue(A, lds + red, cmax, dt);
