@@ -35,7 +35,11 @@
 namespace rsstk {
 
 constexpr int kBatchThreads = 256;  // one box row: at most 4 waves
-constexpr int kBatchPerCU = 2;      // persistent workgroups per CU
+// Persistent workgroups per CU.  A workgroup is one wave per SIMD, so this is
+// also the waves per SIMD the kernel is compiled for (its register budget).
+// Measured with 137-VGPR one-plane strips, three per CU were 0-65% slower
+// than two on every strip choice (more items in flight, each slower).
+constexpr int kBatchPerCU = 2;
 
 struct BoxDev {
   StageArgs s1, s2;  // stage views of the box (pointers into U_all / U1_all)
@@ -160,7 +164,7 @@ __device__ __forceinline__ void signal_done(const BatchState& S, const Pending& 
 // otherwise join the two across the back edge into a loop that thread 0
 // leaves while the rest of its wave goes round without it.
 template <typename ST, int FORM>
-__global__ void __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(3))) batch_kernel(const BoxDev* __restrict__ boxes,
+__global__ void __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(kBatchPerCU))) batch_kernel(const BoxDev* __restrict__ boxes,
                                                             const Item* __restrict__ items,
                                                             BatchState S) {
   extern __shared__ double lds[];
@@ -208,9 +212,9 @@ __global__ void __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per
     if (skip_item) {
       // nothing computed or stored; the item is still signalled done below
     } else if (!st2) {
-      cmax = stage_body2<1, ST, FORM>(B.s1, lds, p * B.groups, dt, bad);
+      cmax = stage_body2<1, ST, FORM, 2>(B.s1, lds, p * B.groups, dt, bad);
     } else {
-      cmax = stage_body2<2, ST, FORM>(B.s2, lds, p * B.groups, dt, bad);
+      cmax = stage_body2<2, ST, FORM, 2>(B.s2, lds, p * B.groups, dt, bad);
     }
     if (bad) atomicOr(S.flags, bad);
     if (st2) {
@@ -366,10 +370,11 @@ static int batch_build(rsst_batch_s* h, void* U) {
     G.nwx = (G.nx + 63) / 64;
     G.ts = groups;
     G.km = km;
+    G.np = 2;
     G.ntile_s = 1;
     G.nchunk = (G.nm + G.km - 1) / G.km;
     G.threads = kBatchThreads;
-    G.lds_bytes = (size_t)carve2(groups, G.nwx).total * sizeof(double);
+    G.lds_bytes = (size_t)carve2(groups, G.nwx, 2).total * sizeof(double);
     if (G.lds_bytes > lds) lds = G.lds_bytes;
     a.ncell = (long long)G.nx * G.nm;
     for (int d = 0; d < 3; ++d) {
@@ -455,8 +460,7 @@ static int batch_prepare(rsst_batch_s* h, void* U, int nsteps) {
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return RSST_E_DEVICE;
-  // at most kBatchPerCU workgroups per CU: more of them (4 fit) make every
-  // run slower (more items in flight, each slower)
+  // at most kBatchPerCU workgroups per CU
   if (per_cu > kBatchPerCU) per_cu = kBatchPerCU;
   h->grid = (per_cu > 0 ? per_cu : 1) * ncu;
   // capture reset + prime + persistent kernel in one graph

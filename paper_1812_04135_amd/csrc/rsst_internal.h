@@ -19,6 +19,7 @@ struct Geometry {
   int ndim;
   int nx, ns, nm;   // extents along x, s, m (ns = 1 unless 3D; nm = 1 in 1D)
   int nwx, ts, km;  // waves per row, rows per tile, planes per chunk
+  int np;           // 2D: planes per march iteration (1 or 2)
   int ntile_s, nchunk;
   int threads;
   size_t lds_bytes;

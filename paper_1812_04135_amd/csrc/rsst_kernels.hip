@@ -183,6 +183,7 @@ __global__ void __launch_bounds__(kDiagThreads) diag_final_kernel(const double* 
 Geometry plan_geometry(int ndim, const int n[3]) {
   Geometry G{};
   G.ndim = ndim;
+  G.np = 1;
   G.nx = n[0];
   G.ns = (ndim == 3) ? n[1] : 1;
   G.nm = (ndim == 3) ? n[2] : (ndim == 2 ? n[1] : 1);
@@ -211,7 +212,14 @@ Geometry plan_geometry(int ndim, const int n[3]) {
     // depend on it, which a GPU test checks for several lengths
     const long long want = ndim == 3 ? 256 : 512;
     int km = ndim == 3 ? 128 : 64;
-    const int kmin = 1;
+    // 2D rows of up to eight waves march two planes per iteration (twice the
+    // independent work per thread and half the barriers per plane) when
+    // two-plane chunks still give every SIMD two waves (2048 waves); smaller
+    // grids run one plane per iteration, in more and shorter marches
+    // (measured: the 512^2 bubble 12.4 -> 13.0 Gcell-updates/s with two,
+    // the 256^2 adjoint forward 4.3 -> 5.4 ms per 400 steps)
+    G.np = (ndim == 2 && G.nwx <= 8 && (long long)((G.nm + 1) / 2) * G.nwx >= 2048) ? 2 : 1;
+    const int kmin = G.np;  // a march iteration takes np planes: no shorter chunk
     while (km > kmin && (long long)G.ntile_s * ((G.nm + km - 1) / km) < want) km >>= 1;
     if (const char* e = getenv("RSST_KM")) {
       const int v = atoi(e);
@@ -222,7 +230,8 @@ Geometry plan_geometry(int ndim, const int n[3]) {
   G.nchunk = (G.nm + G.km - 1) / G.km;
   G.threads = 64 * G.nwx * (ndim == 3 ? G.ts / 2 : G.ts);
   G.lds_bytes = (size_t)(ndim == 3 ? carve3(G.ts, G.nwx).total
-                                    : (ndim == 2 ? carve2(G.ts, G.nwx).total : carve(ndim, G.ts, G.nwx).total)) *
+                                    : (ndim == 2 ? carve2(G.ts, G.nwx, G.np).total
+                                                 : carve(ndim, G.ts, G.nwx).total)) *
                 sizeof(double);
   return G;
 }

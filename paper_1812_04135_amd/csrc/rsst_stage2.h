@@ -2,13 +2,14 @@
 // kernels and the batched persistent kernel.
 //
 // A workgroup holds ts x rows of nx cells (nwx waves each); row r of the
-// workgroup marches y over its own chunk of planes (chunk_base + r).  x
-// neighbours and x plus-face states are exchanged through LDS rows with one
-// ghost slot at each end (periodic wrap or mirror), and every x face flux is
-// formed once, by the cell right of the face, and handed to the cell on its
-// left after a third barrier (by DPP within a wave, one LDS seam value per
-// wave edge).  y is marched: every y face is formed once and carried to the
-// next plane.
+// workgroup marches y over its own chunk of planes (chunk_base + r), NP
+// planes per iteration, so each thread has NP independent cells to
+// interleave and the barriers are shared by NP planes.  x neighbours and x
+// plus-face states are exchanged through LDS rows with one ghost slot at
+// each end (periodic wrap or mirror), and every x face flux is formed once,
+// by the cell right of the face, and handed to the cell on its left after a
+// third barrier (by DPP within a wave, one LDS seam value per wave edge).
+// y is marched: every y face is formed once and carried to the next plane.
 #pragma once
 
 #include "rsst_stage.h"
@@ -17,30 +18,33 @@
 
 namespace rsstk {
 
-// LDS carve-up of a 2D workgroup (doubles): ts rows of nwx waves.
+// LDS carve-up of a 2D workgroup (doubles): ts rows of nwx waves, np planes
+// per iteration.
 struct Carve2 {
   int u, fp, fxs, red, total;
 };
 
-__host__ __device__ inline Carve2 carve2(int ts, int nwx) {
+__host__ __device__ inline Carve2 carve2(int ts, int nwx, int np) {
   constexpr int NV = 4, PL = NV + 3;
-  const int px = 64 * nwx + 2;
+  const int px = 64 * nwx + 2, rows = ts * np;
   Carve2 c;
   int o = 0;
-  c.u = o;   o += ts * NV * px;   // cell states [row][value][slot], slot 1 + i; 0, nx + 1: x ghosts
-  c.fp = o;  o += ts * PL * px;   // x plus-face states, slot 1 + i; slot 0: the left ghost's
-  c.fxs = o; o += ts * NV * nwx;  // x flux at the left edge of each wave
+  c.u = o;   o += rows * NV * px;   // cell states [row][plane][value][slot], slot 1 + i; 0, nx + 1: ghosts
+  c.fp = o;  o += rows * PL * px;   // x plus-face states, slot 1 + i; slot 0: the left ghost's
+  c.fxs = o; o += rows * NV * nwx;  // x flux at the left edge of each wave
   c.red = o; o += 16;
   c.total = o;
   return c;
 }
 
 // One stage of R over one group of 2D strips (row r of the workgroup marches
-// chunk chunk_base + r), returning the thread's largest c_tot of the stage-2
-// output (0 in stage 1) and or-ing non-physical flags into `bad`.  Every row
-// of the workgroup runs the same number of march iterations (G.km), so rows
-// of different chunks share the workgroup's barriers.
-template <int STAGE, typename ST, int FORMX>
+// chunk chunk_base + r, NP planes per iteration), returning the thread's
+// largest c_tot of the stage-2 output (0 in stage 1) and or-ing
+// non-physical flags into `bad`.  Every row of the workgroup runs the same
+// number of march iterations, so rows of different chunks share the
+// workgroup's barriers; planes past a chunk's end are computed on rows held
+// in range and not stored.
+template <int STAGE, typename ST, int FORMX, int NP>
 __device__ __forceinline__ double stage_body2(const StageArgs& A, double* lds, int chunk_base, double dt,
                                               unsigned& bad) {
   constexpr int NDIM = 2, NV = 4, PL = NV + 3;
@@ -52,7 +56,7 @@ __device__ __forceinline__ double stage_body2(const StageArgs& A, double* lds, i
   const Geometry& G = A.geo;
   const int TS = G.ts, nwx = G.nwx;
   const int PX = 64 * nwx + 2;
-  const Carve2 C = carve2(TS, nwx);
+  const Carve2 C = carve2(TS, nwx, NP);
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -75,22 +79,25 @@ __device__ __forceinline__ double stage_body2(const StageArgs& A, double* lds, i
   const int plane = G.nx * SZ;  // bytes per y row
   const int col = i * SZ;
 
-  // the thread's LDS addresses: its cell slot minus one (its left neighbour),
-  // its plus-face slot minus one, and its wave's x seam
-  double* const Urow = lds + C.u + row * (NV * PX);
-  double* const Frow = lds + C.fp + row * (PL * PX);
-  double* const ub = Urow + i;                           // + v PX + {0, 1, 2}: left, own, right
-  double* const fb = Frow + i;                           // + q PX + {0, 1}: left neighbour's, own
-  double* const xs = lds + C.fxs + row * (NV * nwx) + wx;  // + v nwx
+  // the thread's LDS addresses: for plane p of the iteration (at + p UR,
+  // + p FR, + p NV nwx), its cell slot minus one (its left neighbour), its
+  // plus-face slot minus one, and its wave's x seam
+  const int UR = NV * PX, FR = PL * PX;
+  double* const Urow = lds + C.u + row * NP * UR;
+  double* const Frow = lds + C.fp + row * NP * FR;
+  double* const ub = Urow + i;                                 // + p UR + v PX + {0, 1, 2}
+  double* const fb = Frow + i;                                 // + p FR + q PX + {0, 1}
+  double* const xs = lds + C.fxs + row * NP * (NV * nwx) + wx;  // + (p NV + v) nwx
 
-  // FP32 perturbation form: the background in registers, along y (the
-  // march axis: bgA plane k, bgB plane k + 2, loaded per plane) or fixed
-  // for the march (uniform, along x)
+  // FP32 perturbation form: the background in registers, along y (the march
+  // axis: bgc[p] for plane k + p of the iteration, bgn[p] for the planes the
+  // iteration loads, k + 2 + p) or fixed for the march (uniform, along x:
+  // bgc[0])
   const bool bg_on_m = F32 && A.bg_axis == 1;
-  double bgA[NV], bgB[NV];
+  double bgc[NP][NV], bgn[NP][NV];
   const __amdgpu_buffer_rsrc_t bgr = field_rsrc(A.bg, F32 ? (long long)NV * A.nbg * 8 : 0);
   if constexpr (F32) {
-    if (!bg_on_m) load_bg<NV>(bgr, A.nbg, A.bg_axis == 0 ? i : 0, bgA);
+    if (!bg_on_m) load_bg<NV>(bgr, A.nbg, A.bg_axis == 0 ? i : 0, bgc[0]);
   }
   // FP64 state of stored values: FP32 with the background bz; FP64 with the
   // mirror sign and a hydrostatic wall's carried pressure (lever)
@@ -107,6 +114,8 @@ __device__ __forceinline__ double stage_body2(const StageArgs& A, double* lds, i
   // stage 2 writes the new state in place over the step-start state
   const Field32 uout = STAGE == 2 ? unp : make_field<false>(A.uout, A.ncell, NV, SZ, plane);
 
+  // the march window: planes k and k + 1 (finished), the slope at k and the
+  // flux at k - 1/2
   double q0[NV], q1[NV], sm0[NV], Fm_lo[NV];
   double cmax = 0.0;
   const int k0l = min(k0, G.nm - 1);  // rows past the grid march in range
@@ -122,7 +131,7 @@ __device__ __forceinline__ double stage_body2(const StageArgs& A, double* lds, i
         if (bg_on_m) load_bg<NV>(bgr, A.nbg, kk, bz);
         else {
 #pragma unroll
-          for (int v = 0; v < NV; ++v) bz[v] = bgA[v];
+          for (int v = 0; v < NV; ++v) bz[v] = bgc[0][v];
         }
       }
       fin(raw, n ? NDIM : -1, bz, HYD ? hydro_lever(k0l + q, G.nm, rm_lo, rm_hi, A.dx[1], A.g[1]) : 0.0, u);
@@ -142,131 +151,171 @@ __device__ __forceinline__ double stage_body2(const StageArgs& A, double* lds, i
     flux2<NDIM, 1>(fl, fr, Fm_lo);
   }
 
-  for (int it = 0; it < G.km; ++it) {
+  for (int it = 0; it < G.km; it += NP) {
     const int kraw = k0 + it;
-    const bool kval = kraw < k1;
-    const int k = min(kraw, G.nm - 1);  // row used for loads and stores
-    // ---- loads for this plane: the row two ahead and the step-start state
-    // (stored values now, finished where first used)
-    ST q2r[NV], unr[NV];
-    bool q2n;
-    const int q2k = map_index(k + 2, G.nm, rm_lo, rm_hi, q2n);
-    const double q2lev = HYD ? hydro_lever(k + 2, G.nm, rm_lo, rm_hi, A.dx[1], A.g[1]) : 0.0;
-    if constexpr (F32) {
-      if (bg_on_m) {
-        load_bg<NV>(bgr, A.nbg, k, bgA);
-        load_bg<NV>(bgr, A.nbg, q2k, bgB);
+    // ---- loads for this iteration: the NP rows after the window (k + 2 ..
+    // k + 1 + NP) and the step-start state of its cells (stored values now,
+    // finished where first used)
+    int kc[NP];    // row of cell p, held in range
+    bool kval[NP]; // cell p is in the chunk
+    ST wr[NP][NV], unr[NP][NV];
+    bool wn[NP];
+    double wlev[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      kc[p] = min(kraw + p, G.nm - 1);
+      kval[p] = kraw + p < k1;
+      const int kq = min(kraw, G.nm - 1) + 2 + p;
+      const int kk = map_index(kq, G.nm, rm_lo, rm_hi, wn[p]);
+      wlev[p] = HYD ? hydro_lever(kq, G.nm, rm_lo, rm_hi, A.dx[1], A.g[1]) : 0.0;
+      if constexpr (F32) {
+        if (bg_on_m) {
+          load_bg<NV>(bgr, A.nbg, kc[p], bgc[p]);
+          load_bg<NV>(bgr, A.nbg, kk, bgn[p]);
+        }
       }
+      load_cell_raw<NDIM, ST>(uin, kk, col, wr[p]);
+      if constexpr (STAGE == 2) load_cell_raw<NDIM, ST>(unp, kc[p], col, unr[p]);
     }
-    load_cell_raw<NDIM, ST>(uin, q2k, col, q2r);
-    if constexpr (STAGE == 2) load_cell_raw<NDIM, ST>(unp, k, col, unr);
+    // the cells of this iteration: q[0] = q0, q[1] = q1 (NP = 2)
+    double q[NP][NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      q[0][v] = q0[v];
+      if constexpr (NP == 2) q[1][v] = q1[v];
+    }
 
-    // ---- P1: publish the cell state, and the x ghosts
-    if (pub) {
+    // ---- P1: publish the cell states, and the x ghosts
 #pragma unroll
-      for (int v = 0; v < NV; ++v) ub[v * PX + 1] = q0[v];
-    }
-    if (first_x || last_x) {
-      // cell 0: periodic, the ghost right of the last cell; wall, the mirror
-      // left of cell 0.  The last cell: periodic, the ghost left of cell 0;
-      // wall, the mirror right of the last cell.
-      double* ur = Urow + (first_x == x_per ? G.nx + 1 : 0);
+    for (int p = 0; p < NP; ++p) {
+      if (pub) {
 #pragma unroll
-      for (int v = 0; v < NV; ++v) ur[v * PX] = (v == 1 && !x_per) ? -q0[v] : q0[v];
+        for (int v = 0; v < NV; ++v) ub[p * UR + v * PX + 1] = q[p][v];
+      }
+      if (first_x || last_x) {
+        // cell 0: periodic, the ghost right of the last cell; wall, the
+        // mirror left of cell 0.  The last cell: periodic, the ghost left of
+        // cell 0; wall, the mirror right of the last cell.
+        double* ur = Urow + p * UR + (first_x == x_per ? G.nx + 1 : 0);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) ur[v * PX] = (v == 1 && !x_per) ? -q[p][v] : q[p][v];
+      }
     }
     __syncthreads();  // B1
 
-    // ---- P2: the x slope and the plus-face state (published)
-    double h[NV];
+    // ---- P2: the x slopes and the plus-face states (published)
+    double h[NP][NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) h[v] = mc_half(q0[v] - ub[v * PX], ub[v * PX + 2] - q0[v]);
-    {
+    for (int p = 0; p < NP; ++p) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        h[p][v] = mc_half(q[p][v] - ub[p * UR + v * PX], ub[p * UR + v * PX + 2] - q[p][v]);
       Face<NV> fp;
-      make_face<NDIM, 0, EXT>(q0, h, true, K, fp);
-      if (pub) put_face(fb + 1, PX, fp);
-      if (x_per && last_x) put_face(Frow, PX, fp);  // the periodic ghost left of cell 0
+      make_face<NDIM, 0, EXT>(q[p], h[p], true, K, fp);
+      if (pub) put_face(fb + p * FR + 1, PX, fp);
+      if (x_per && last_x) put_face(Frow + p * FR, PX, fp);  // the periodic ghost left of cell 0
     }
     __syncthreads();  // B2
 
-    // ---- P3: the x flux at the cell's left face, published at wave edges
-    double Fx_lo[NV];
-    {
+    // ---- P3: the x flux at each cell's left face, published at wave edges
+    double Fx_lo[NP][NV];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
       Face<NV> fm, pl;
-      make_face<NDIM, 0, EXT>(q0, h, false, K, fm);
-      get_face(fb, PX, pl);  // slot i: the plus face of cell i - 1
+      make_face<NDIM, 0, EXT>(q[p], h[p], false, K, fm);
+      get_face(fb + p * FR, PX, pl);  // slot i: the plus face of cell i - 1
       if (!x_per) {
         if (first_x) pl = mirror<NDIM, 0>(fm);
       }
-      flux2<NDIM, 0>(pl, fm, Fx_lo);
+      flux2<NDIM, 0>(pl, fm, Fx_lo[p]);
       if (lane == 0 && !wave_idle) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) xs[v * nwx] = Fx_lo[v];
+        for (int v = 0; v < NV; ++v) xs[(p * NV + v) * nwx] = Fx_lo[p][v];
       }
     }
     __syncthreads();  // B3
 
-    // ---- P4: the flux at the cell's right face, the y direction, then the
+    // ---- P4: the flux at each cell's right face, the y direction, then the
     // rate, the RK update and the store
-    double Dl[NV];
-    {
+    double Dl[NP][NV];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
       double Fx_hi[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Fx_hi[v] = from_right(Fx_lo[v]);
+      for (int v = 0; v < NV; ++v) Fx_hi[v] = from_right(Fx_lo[p][v]);
       if (last_x) {
         if (x_per) {
 #pragma unroll
-          for (int v = 0; v < NV; ++v) Fx_hi[v] = xs[v * nwx - wx];
+          for (int v = 0; v < NV; ++v) Fx_hi[v] = xs[(p * NV + v) * nwx - wx];
         } else {
           Face<NV> fp;
-          get_face(fb + 1, PX, fp);
+          get_face(fb + p * FR + 1, PX, fp);
           flux2<NDIM, 0>(fp, mirror<NDIM, 0>(fp), Fx_hi);
         }
       } else if (lane == 63 && xin && !wave_idle) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) Fx_hi[v] = xs[v * nwx + 1];
+        for (int v = 0; v < NV; ++v) Fx_hi[v] = xs[(p * NV + v) * nwx + 1];
       }
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Dl[v] = -(Fx_hi[v] - Fx_lo[v]) * hx;
+      for (int v = 0; v < NV; ++v) Dl[p][v] = -(Fx_hi[v] - Fx_lo[p][v]) * hx;
     }
-    double q2[NV];
-    if (F32 && bg_on_m) fin(q2r, q2n ? NDIM : -1, bgB, 0.0, q2);
-    else fin(q2r, q2n ? NDIM : -1, bgA, q2lev, q2);
-    {
+    // the window's next rows, finished: wq[p] is row k + 2 + p
+    double wq[NP][NV];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      if (F32 && bg_on_m) fin(wr[p], wn[p] ? NDIM : -1, bgn[p], 0.0, wq[p]);
+      else fin(wr[p], wn[p] ? NDIM : -1, bgc[0], wlev[p], wq[p]);
+    }
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      // the slope at k + p + 1 and the flux at k + p + 1/2
+      // the rows after cell p: the window is q0, q1, wq[0], ..., wq[NP - 1]
+      const double (&qn)[NV] = p == 0 ? q1 : wq[p == 0 ? 0 : p - 1];
+      const double (&qnn)[NV] = wq[p];
       double sm1[NV], Fm_hi[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) sm1[v] = mc_half(q1[v] - q0[v], q2[v] - q1[v]);
+      for (int v = 0; v < NV; ++v) sm1[v] = mc_half(qn[v] - q[p][v], qnn[v] - qn[v]);
       Face<NV> fl, fr;
-      make_face<NDIM, 1, EXT>(q0, sm0, true, K, fl);
-      make_face<NDIM, 1, EXT>(q1, sm1, false, K, fr);
+      make_face<NDIM, 1, EXT>(q[p], sm0, true, K, fl);
+      make_face<NDIM, 1, EXT>(qn, sm1, false, K, fr);
       flux2<NDIM, 1>(fl, fr, Fm_hi);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        Dl[v] = fma(-(Fm_hi[v] - Fm_lo[v]), hy, Dl[v]);
+        Dl[p][v] = fma(-(Fm_hi[v] - Fm_lo[v]), hy, Dl[p][v]);
         Fm_lo[v] = Fm_hi[v];
         sm0[v] = sm1[v];
       }
-    }
-    double Rt[NV];
-    const unsigned b = rsst_rate<NDIM, FORM, EXT>(q0, Dl, K, g, Rt);
-    double un[NV];
-    if constexpr (STAGE == 2) fin(unr, -1, bgA, 0.0, un);
-    if (active && kval) {
-      bad |= b;
-      double out[NV];
+      double Rt[NV];
+      const unsigned b = rsst_rate<NDIM, FORM, EXT>(q[p], Dl[p], K, g, Rt);
+      double un[NV];
+      if constexpr (STAGE == 2) fin(unr[p], -1, bg_on_m ? bgc[p] : bgc[0], 0.0, un);
+      if (active && kval[p]) {
+        bad |= b;
+        double out[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        double y = fma(dt, Rt[v], q0[v]);
-        if constexpr (STAGE == 2) y = 0.5 * (un[v] + y);
-        double bgv = 0.0;
-        if constexpr (F32) bgv = bgA[v];
-        const ST st = (ST)(y - bgv);
-        buf_store<ST>(uout.r, col, uout.soff(v, k), st);
-        out[v] = (double)st + bgv;
+        for (int v = 0; v < NV; ++v) {
+          double y = fma(dt, Rt[v], q[p][v]);
+          if constexpr (STAGE == 2) y = 0.5 * (un[v] + y);
+          double bgv = 0.0;
+          if constexpr (F32) bgv = bg_on_m ? bgc[p][v] : bgc[0][v];
+          const ST st = (ST)(y - bgv);
+          buf_store<ST>(uout.r, col, uout.soff(v, kc[p]), st);
+          out[v] = (double)st + bgv;
+        }
+        if constexpr (STAGE == 2) cmax = fmax(cmax, cell_ctot<NDIM, EXT>(out, K));
       }
-      if constexpr (STAGE == 2) cmax = fmax(cmax, cell_ctot<NDIM, EXT>(out, K));
     }
+    // the window moves NP rows
 #pragma unroll
-    for (int v = 0; v < NV; ++v) { q0[v] = q1[v]; q1[v] = q2[v]; }
+    for (int v = 0; v < NV; ++v) {
+      if constexpr (NP == 2) {
+        q0[v] = wq[0][v];
+        q1[v] = wq[1][v];
+      } else {
+        q0[v] = q1[v];
+        q1[v] = wq[0][v];
+      }
+    }
   }
   return cmax;
 }

@@ -35,7 +35,8 @@ __global__ void __launch_bounds__(NDIM == 3 ? kMaxThreads3 : 1024) stage_kernel(
   const int L = xcd_tile(blockIdx.x, gridDim.x);
   const int tile_s = L % G.ntile_s;
   const int chunk_base = (L / G.ntile_s) * (NDIM == 3 ? 1 : G.ts);
-  const int red = NDIM == 3 ? carve3(G.ts, NWXC).red : (NDIM == 2 ? carve2(G.ts, G.nwx).red : carve(NDIM, G.ts, G.nwx).red);
+  static_assert(NDIM != 2, "2D grids run stage_kernel2d");
+  const int red = NDIM == 3 ? carve3(G.ts, NWXC).red : carve(NDIM, G.ts, G.nwx).red;
   // a CFL step's dt: formed by stage 1 from the maxima of the state it
   // reads, recorded for stage 2
   double dt = A.dt_fixed;
@@ -50,20 +51,43 @@ __global__ void __launch_bounds__(NDIM == 3 ? kMaxThreads3 : 1024) stage_kernel(
   unsigned bad = 0;
   double cmax;
   if constexpr (NDIM == 3) cmax = stage_body3<STAGE, ST, FORM, NWXC, BIG>(A, lds, tile_s, chunk_base, dt, bad);
-  else if constexpr (NDIM == 2) cmax = stage_body2<STAGE, ST, FORM>(A, lds, chunk_base, dt, bad);
   else cmax = stage_body<NDIM, STAGE, ST, FORM, NWXC, BIG>(A, lds, tile_s, chunk_base, dt, bad);
   if (bad) atomicOr((unsigned*)(A.scal + kFlags), bad);
   if constexpr (STAGE == 2) cfl_epilogue(A, lds + red, cmax, dt);
 }
 
-template <int NDIM, int STAGE, typename ST, int FORM, int NWXC>
-static hipError_t launch_stage_k(const StageArgs& a, hipStream_t s) {
+// 2D grids: NP planes of y per march iteration (the geometry's np): two for
+// large grids with rows of up to eight waves (512 threads at most), else one
+// (up to 1024 threads, fewer registers per thread).
+template <int STAGE, typename ST, int FORM, int NP>
+__global__ void __launch_bounds__(NP == 2 ? 512 : 1024) stage_kernel2d(const StageArgs A) {
+  extern __shared__ double lds[];
+  const Geometry& G = A.geo;
+  const int L = xcd_tile(blockIdx.x, gridDim.x);
+  const int chunk_base = L * G.ts;
+  const int red = carve2(G.ts, G.nwx, NP).red;
+  double dt = A.dt_fixed;
+  if (!(A.dt_fixed > 0.0)) {
+    if constexpr (STAGE == 1) {
+      dt = cfl_dt_from_blocks(A, lds + red);
+      if (blockIdx.x == 0 && threadIdx.x == 0) A.scal[kDtCur] = dt;
+    } else {
+      dt = A.scal[kDtCur];
+    }
+  }
+  unsigned bad = 0;
+  const double cmax = stage_body2<STAGE, ST, FORM, NP>(A, lds, chunk_base, dt, bad);
+  if (bad) atomicOr((unsigned*)(A.scal + kFlags), bad);
+  if constexpr (STAGE == 2) cfl_epilogue(A, lds + red, cmax, dt);
+}
+
+// One launch of a stage kernel over the geometry's grid.  The kernel's LDS
+// limit is raised only when a larger tile needs it (lds_set: the limit set
+// so far per device, owned by the kernel's launcher), so launches of a known
+// shape (e.g. under HIP graph capture) make no attribute call.
+static hipError_t launch_geo(void (*kern)(StageArgs), int* lds_set, const StageArgs& a, hipStream_t s) {
   const Geometry& G = a.geo;
   const dim3 grid((unsigned)(G.ntile_s * G.nchunk)), block((unsigned)G.threads);
-  auto kern = stage_kernel<NDIM, STAGE, ST, FORM, NWXC, kBig>;
-  // raise the kernel's LDS limit only when a larger tile needs it, so launches
-  // of a known shape (e.g. under HIP graph capture) make no attribute call
-  static int lds_set[64] = {0};
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
   if ((int)G.lds_bytes > lds_set[dev]) {
@@ -74,6 +98,18 @@ static hipError_t launch_stage_k(const StageArgs& a, hipStream_t s) {
   }
   hipLaunchKernelGGL(kern, grid, block, G.lds_bytes, s, a);
   return hipGetLastError();
+}
+
+template <int NDIM, int STAGE, typename ST, int FORM, int NWXC>
+static hipError_t launch_stage_k(const StageArgs& a, hipStream_t s) {
+  static int lds_set[64] = {0};
+  return launch_geo(stage_kernel<NDIM, STAGE, ST, FORM, NWXC, kBig>, lds_set, a, s);
+}
+
+template <int STAGE, typename ST, int FORM, int NP>
+static hipError_t launch_stage_2d(const StageArgs& a, hipStream_t s) {
+  static int lds_set[64] = {0};
+  return launch_geo(stage_kernel2d<STAGE, ST, FORM, NP>, lds_set, a, s);
 }
 
 template <int NDIM, int STAGE, typename ST, int FORM>
@@ -87,6 +123,8 @@ static hipError_t launch_stage_t(const StageArgs& a, hipStream_t s) {
       case 8: return launch_stage_k<NDIM, STAGE, ST, FORM, 8>(a, s);
       default: return hipErrorInvalidValue;
     }
+  } else if constexpr (NDIM == 2) {
+    return a.geo.np == 2 ? launch_stage_2d<STAGE, ST, FORM, 2>(a, s) : launch_stage_2d<STAGE, ST, FORM, 1>(a, s);
   } else {
     return launch_stage_k<NDIM, STAGE, ST, FORM, 0>(a, s);
   }
