@@ -12,26 +12,32 @@
 //
 // Work decomposition (x = axis 0, contiguous in memory):
 //   * lanes run along x: a workgroup holds whole rows of nx cells spread
-//     over nwx = ceil(nx/64) waves, so x needs no halo: neighbours come from
-//     the adjacent lane by DPP, from the adjacent wave through a few LDS
-//     "seam" slots, and periodic or mirror walls are applied in-row;
-//   * 3D: ts rows along y are stacked in the workgroup; y neighbours and
-//     y-face states are exchanged through LDS, and the two rows just outside
-//     the tile are read from global memory by the edge rows;
-//   * the last axis (z in 3D, y in 2D) is marched: each thread keeps three
-//     planes of its own column in registers, so every z face is computed
-//     once and z needs no exchange at all;
+//     over nwx = ceil(nx/64) waves, so x needs no halo;
+//   * 2D and 3D: x neighbours and x plus-face states go through LDS rows
+//     with a ghost slot at each end (periodic wrap or mirror); every x flux
+//     is formed once, by the cell right of the face, and reaches the cell on
+//     its left by DPP within a wave and through one LDS seam value per wave
+//     edge after a third barrier (rsst_stage2.h, rsst_stage3.h).  1D keeps
+//     its row in one workgroup with DPP neighbours and LDS seams, the
+//     wave-edge fluxes formed by both waves (rsst_stage1.h);
+//   * 3D: each thread owns two adjacent y rows of its column, and a tile of
+//     eight waves stacks 2R rows; the y face between a thread's rows is
+//     formed in registers, the one between thread-rows once and handed over
+//     in LDS, and the tile's two outer faces by each of the two tiles that
+//     share them (the same face states and code, so the same bits), from the
+//     rows just outside the tile, which the edge thread-rows read from
+//     global memory a plane ahead;
+//   * the last axis (z in 3D, y in 2D) is marched: each thread keeps its
+//     column's planes in registers, so every z face is computed once and
+//     carried to the next plane; large 2D grids march two planes per
+//     iteration;
 //   * every face state (U +- sigma/2, its pressure, c_tot and normal
-//     velocity) is computed once, by the cell that owns it; a z flux (the
-//     marched axis) is computed once and carried to the next plane, an
-//     interior x flux once and handed to the lane above by DPP; the x flux at
-//     a wave edge is formed by both waves that share it, and a y flux inside
-//     a 3D tile by both rows (the same face states and code, so the same
-//     bits), and the y flux at a tile's outer face by each of the two tiles.
+//     velocity) is computed once, by the cell that owns it;
 //   * workgroup ids are remapped so that consecutive tiles (which share
 //     halo rows) run on the same XCD and share its L2.
 #include <cstdlib>
 
+#include "rsst_stage1.h"
 #include "rsst_stage2.h"
 #include "rsst_stage3.h"
 
@@ -231,7 +237,7 @@ Geometry plan_geometry(int ndim, const int n[3]) {
   G.threads = 64 * G.nwx * (ndim == 3 ? G.ts / 2 : G.ts);
   G.lds_bytes = (size_t)(ndim == 3 ? carve3(G.ts, G.nwx).total
                                     : (ndim == 2 ? carve2(G.ts, G.nwx, G.np).total
-                                                 : carve(ndim, G.ts, G.nwx).total)) *
+                                                 : carve1(G.nwx).total)) *
                 sizeof(double);
   return G;
 }

@@ -3,6 +3,7 @@
 // Compiled once per (RSST_INST_NDIM, RSST_INST_ST, RSST_INST_BIG) so the
 // library builds in parallel objects; RSST_INST_BIG = 1 builds the 3D
 // kernels that address states of 2 GiB or more (Field64).
+#include "rsst_stage1.h"
 #include "rsst_stage2.h"
 #include "rsst_stage3.h"
 
@@ -36,7 +37,7 @@ __global__ void __launch_bounds__(NDIM == 3 ? kMaxThreads3 : 1024) stage_kernel(
   const int tile_s = L % G.ntile_s;
   const int chunk_base = (L / G.ntile_s) * (NDIM == 3 ? 1 : G.ts);
   static_assert(NDIM != 2, "2D grids run stage_kernel2d");
-  const int red = NDIM == 3 ? carve3(G.ts, NWXC).red : carve(NDIM, G.ts, G.nwx).red;
+  const int red = NDIM == 3 ? carve3(G.ts, NWXC).red : carve1(G.nwx).red;
   // a CFL step's dt: formed by stage 1 from the maxima of the state it
   // reads, recorded for stage 2
   double dt = A.dt_fixed;
@@ -51,7 +52,7 @@ __global__ void __launch_bounds__(NDIM == 3 ? kMaxThreads3 : 1024) stage_kernel(
   unsigned bad = 0;
   double cmax;
   if constexpr (NDIM == 3) cmax = stage_body3<STAGE, ST, FORM, NWXC, BIG>(A, lds, tile_s, chunk_base, dt, bad);
-  else cmax = stage_body<NDIM, STAGE, ST, FORM, NWXC, BIG>(A, lds, tile_s, chunk_base, dt, bad);
+  else cmax = stage_body1<STAGE, ST, FORM>(A, lds, dt, bad);
   if (bad) atomicOr((unsigned*)(A.scal + kFlags), bad);
   if constexpr (STAGE == 2) cfl_epilogue(A, lds + red, cmax, dt);
 }
@@ -195,7 +196,7 @@ __global__ void __launch_bounds__(1024) steps1d_kernel(const StageArgs a1, const
   constexpr int NV = 3;
   extern __shared__ double lds[];
   const Geometry& G = a1.geo;
-  double* red = lds + carve(1, G.ts, G.nwx).red;
+  double* red = lds + carve1(G.nwx).red;
   const bool cfl = !(a1.dt_fixed > 0.0);
   double t = a1.scal[kTime];
   double dt = a1.dt_fixed;
@@ -220,14 +221,14 @@ __global__ void __launch_bounds__(1024) steps1d_kernel(const StageArgs a1, const
     if (cfl && a1.t_end > 0.0 && !(dt > 0.0)) break;
 #pragma unroll
     for (int v = 0; v < NV; ++v) c.out[v] = c.in[v];
-    stage_body<1, 1, ST, FORM, 0, false, true>(a1, lds, 0, 0, dt, bad, &c);
+    stage_body1<1, ST, FORM, true>(a1, lds, dt, bad, &c);
     __syncthreads();
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       c.un[v] = c.in[v];
       c.in[v] = c.out[v];
     }
-    const double cm = stage_body<1, 2, ST, FORM, 0, false, true>(a2, lds, 0, 0, dt, bad, &c);
+    const double cm = stage_body1<2, ST, FORM, true>(a2, lds, dt, bad, &c);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       c.in[v] = c.out[v];
