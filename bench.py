@@ -47,6 +47,17 @@ def traffic_from_profile(kernel_tag: str, version: str):
     return d.get("bytes_per_launch")
 
 
+def profile_json(name: str, version: str):
+    """A committed per-run byte summary (profiles/<name>.json) if it was taken
+    on this library revision; else None."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    return d if d.get("version") == version else None
+
+
 def alu_view(version: str, value: float):
     """The FP64-ALU side of the headline kernels from the committed SQ counter
     summary (if taken on this revision): VALU wave-instructions per
@@ -59,11 +70,14 @@ def alu_view(version: str, value: float):
     text = open(path).read()
     if f"`{version}`" not in text:
         return None
-    per = {}
+    per, col = {}, None
     for line in text.splitlines():
+        cells = [c.strip() for c in line.split("|")]
+        if col is None and "VALU wave-instr per cell" in cells:
+            col = cells.index("VALU wave-instr per cell")
         for st in (1, 2):
-            if line.startswith(f"| `void stage_kernel<3, {st}, double, 1, 4>"):
-                per[st] = float(line.split("|")[2])
+            if col is not None and line.startswith(f"| `void stage_kernel<3, {st}, double, 1, 4>"):
+                per[st] = float(cells[col])
     if len(per) != 2:
         return None
     wi = per[1] + per[2]
@@ -100,6 +114,21 @@ def pert_err(Ug, pert, nv):
     sm = max(sc[1:nv - 1])
     sc = [sc[0]] + [sm] * (nv - 2) + [sc[nv - 1]]
     return max(float(np.abs(Ug[v] - pert[v]).max() / sc[v]) for v in range(nv))
+
+
+def batch_roofline(version, prec, eff_gbs, cell_updates_s):
+    """HBM view of a batched run: algorithmic bytes (5 x 4 values per
+    cell-update) over the run time against the 8 TB/s peak, and the HBM bytes
+    the committed counters of this revision measured per cell-update."""
+    out = {"bound": "hbm", "achieved": round(eff_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(eff_gbs / HBM_PEAK_GBS, 4), "traffic_GBs": None}
+    t = profile_json("traffic_batch512.json", version)
+    if t:
+        b = t["bytes_per_cell_update"]["float" if prec == "fp32_pert" else "double"]
+        out["traffic_GBs"] = round(b * cell_updates_s / 1e9, 1)
+        out["traffic_frac"] = round(b * cell_updates_s / 1e9 / HBM_PEAK_GBS, 4)
+        out["traffic_source"] = t["source"]
+    return out
 
 
 def bench_batch(R, W, np, torch, stream, args):
@@ -163,6 +192,8 @@ def bench_batch(R, W, np, torch, stream, args):
             "ms_per_run": round(best, 4), "ms_per_run_all": [round(x, 4) for x in ms],
             "Gcell_updates_s": round(ncell * nst / (best * 1e-3) / 1e9, 4),
             "effective_GBs": round(5 * 4 * es * ncell * nst / (best * 1e-3) / 1e9, 1),
+            "roofline": batch_roofline(R.rsst_version(), prec, 5 * 4 * es * ncell * nst / (best * 1e-3) / 1e9,
+                                       ncell * nst / (best * 1e-3)),
             "strip_rows": tiles, "tiles_from_cache": cached,
             "err_vs_oracle": max(errs), "err_kind": "perturbation scale (1e-5)" if prec == "fp32_pert"
             else "natural scales (1e-12)",
@@ -311,6 +342,19 @@ def bench_rt_paper(R, W, np, torch, stream, n=1024, log=None):
     return out
 
 
+def adjoint_roofline(version, step_ms):
+    """HBM bytes of one backward step (the segment's forward re-run, the
+    stage-1 recompute and two VJPs) from the committed counters of this
+    revision, over the measured backward time per step, against 8 TB/s."""
+    t = profile_json("traffic_adjoint_bubble256.json", version)
+    if not t:
+        return None
+    gbs = t["bytes_per_backward_step"] / (step_ms * 1e-3) / 1e9
+    return {"bound": "latency", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_backward_step": round(t["bytes_per_backward_step"]),
+            "source": t["source"]}
+
+
 def bench_adjoint(R, W, np, torch, stream, args):
     """Gradient of the final kinetic energy of the 256^2 bubble (xi = 10,
     400 fixed-dt steps, checkpoints every 20) w.r.t. the initial density
@@ -382,6 +426,7 @@ def bench_adjoint(R, W, np, torch, stream, args):
         "backward_ms_per_step": round(adj_step_ms, 5),
         "Gcell_updates_s": round(ncell * nsteps / (bwd_ms * 1e-3) / 1e9, 4),
         "backward_over_forward": round(bwd_ms / fwd_ms, 3),
+        "roofline": adjoint_roofline(R.rsst_version(), adj_step_ms),
         "fd_rel_err_median": float(np.median(errs)), "fd_rel_err_max": float(errs.max()),
         "fd_within_bar": bool(errs.max() <= 1e-4),
         "fd": "central differences, h = 1e-6, 32 smooth density directions; "
