@@ -154,7 +154,7 @@ def bench_batch(R, W, np, torch, stream, args):
             tiles, cached = [int(x) for x in args.batch_tiles.split(",")], False
             B.set_tiles(tiles)
         else:
-            tiles, tune_ms, cached = B.autotune(U0, nsteps=20)
+            tiles, tune_ms, cached = B.autotune(U0, nsteps=40)
         U.copy_(U0)
         B.run(U, nst, stream)  # warm
         ms = []

@@ -5,9 +5,9 @@ unit of work one workgroup takes from the queue.  Short strips give more
 items (better balance, shorter dependency waits) but pay the march start-up
 (four planes loaded and one face flux computed before the first row) more
 often.  The best length depends on the box widths (1..4 waves per row), the
-mix of sizes and the precision, so it is measured: a coordinate sweep over
-the four width classes, each candidate timed on whole runs of the caller's
-batch (HIP events on the launch stream, best of `reps`), on a scratch copy
+mix of sizes and the precision, so it is measured: coordinate sweeps over
+the four width classes (repeated from the result while they change it, at
+most `passes`), each candidate timed on whole runs of the caller's batch (HIP events on the launch stream, best of `reps`), on a scratch copy
 of the state so the caller's state is not advanced.  Results are cached in a
 JSON file keyed by device, precision, form and the batch's width/height
 histogram.
@@ -65,7 +65,7 @@ def _time_run(batch, U, nsteps, reps, stream):
 
 
 def tune(batch, U, nsteps: int = 20, candidates=CANDIDATES, reps: int = 2, cache: str | None = DEFAULT_CACHE,
-         stream=None, retune: bool = False, log=None):
+         stream=None, retune: bool = False, log=None, passes: int = 2):
     """Pick strip rows for `batch` (a paper_1812_04135_amd.Batch) and set them.
 
     U is the packed state of the batch; it is only read (runs go to a
@@ -100,13 +100,19 @@ def tune(batch, U, nsteps: int = 20, candidates=CANDIDATES, reps: int = 2, cache
         return times[tt]
 
     best = measure(tiles)
-    for c in present:
-        for cand in candidates:
-            t = list(tiles)
-            t[c] = cand
-            ms = measure(t)
-            if ms < best:
-                best, tiles = ms, t
+    # the width classes share the GPU, so one class's best length depends on
+    # the others': sweep again from the result until a pass changes nothing
+    for _ in range(max(1, int(passes))):
+        start = list(tiles)
+        for c in present:
+            for cand in candidates:
+                t = list(tiles)
+                t[c] = cand
+                ms = measure(t)
+                if ms < best:
+                    best, tiles = ms, t
+        if tiles == start:
+            break
     batch.set_tiles(tiles)
     del scratch
     rsst_batch_set_times(batch.h, times0, flags0, stream)

@@ -113,6 +113,11 @@ CASES = [
     (3, [65, 6, 5], ["periodic", "periodic", "reflect"], [0.0, 0.0, -0.5], "pvs"),
     (3, [129, 5, 4], ["reflect", "periodic", "periodic"], None, "dvs"),
     (3, [257, 4, 4], ["periodic"] * 3, None, "pvs"),
+    # 2D grids large enough for two planes per march iteration (rows of up to
+    # eight waves, two-plane chunks giving 2048 waves): an odd row count (the
+    # last chunk's second plane lies past the grid), 64 m + 1 cells, walls
+    (2, [449, 515], ["periodic", "reflect"], [0.0, -0.5], "pvs"),
+    (2, [512, 520], ["reflect", "periodic"], [0.3, 0.0], "dms"),
 ]
 
 
