@@ -164,6 +164,16 @@ int rsst_step(rsst_handle h, void* U, double dt_fixed, void* stream);
  * stage number. */
 int rsst_stage(rsst_handle h, void* U, int stage, double dt_fixed, void* stream);
 
+/* One rsst_step out of place: U1 = U + dt R(U) into the caller's U1 and
+ *   Unext = (U + (U1 + dt R(U1))) / 2,
+ * U unchanged.  Same kernels, dt rule and results as rsst_step (Unext holds
+ * the bits rsst_step would leave in U; t and the recorded maxima advance the
+ * same way).  U1, Unext: device arrays of U's type and size that overlap
+ * neither U nor each other (RSST_E_ARG where two of the three pointers are
+ * equal).  For callers that keep a trajectory with its stage values, e.g.
+ * to hand U1 to rsst_adjoint_step_u1. */
+int rsst_step_out(rsst_handle h, const void* U, void* U1, void* Unext, double dt_fixed, void* stream);
+
 /* nsteps calls of rsst_step, with the same results.  A 1D grid runs as one
  * workgroup, so for ndim = 1 all nsteps steps are one launch (both stages,
  * the CFL maximum and the next dt of every step inside it, U written once at
@@ -236,6 +246,13 @@ int rsst_step_noalloc(const rsst_config* cfg, void* U, double dt_fixed, uint32_t
  * in the handle's stage buffer, so the call must not fall between the two
  * stages of a forward rsst_stage pair on the same handle.  Enqueues only. */
 int rsst_adjoint_step(rsst_handle h, const void* U, double* lam, double dt, double* dJdxi, void* stream);
+
+/* rsst_adjoint_step with the step's stage value given: U1 = U + dt R(U) as
+ * rsst_step_out left it for this U and dt (device FP64, read only), so it is
+ * not recomputed and the handle's stage buffer is not touched.  Same results
+ * as rsst_adjoint_step, bit for bit. */
+int rsst_adjoint_step_u1(rsst_handle h, const void* U, const void* U1, double* lam, double dt, double* dJdxi,
+                         void* stream);
 
 /* ---- Batched boxes ------------------------------------------------------
  * Many independent 2D boxes (each with its own size, xi, gravity, boundaries

@@ -88,12 +88,15 @@ def lib():
         L.rsst_batch_poll.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32)]
         L.rsst_batch_destroy.argtypes = [vp]
         L.rsst_adjoint_step.argtypes = [vp, vp, vp, ctypes.c_double, vp, vp]
+        L.rsst_adjoint_step_u1.argtypes = [vp, vp, vp, vp, ctypes.c_double, vp, vp]
+        L.rsst_step_out.argtypes = [vp, vp, vp, vp, ctypes.c_double, vp]
         L.rsst_batch_plan.argtypes = [ctypes.POINTER(rsst_config), ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                       ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         for name in ("rsst_init", "rsst_prime", "rsst_step", "rsst_stage", "rsst_steps", "rsst_get_time",
                      "rsst_diag", "rsst_poll", "rsst_destroy", "rsst_batch_init", "rsst_batch_set_tiles",
                      "rsst_batch_get_tiles", "rsst_batch_run", "rsst_batch_times", "rsst_batch_poll",
-                     "rsst_batch_destroy", "rsst_batch_plan", "rsst_adjoint_step"):
+                     "rsst_batch_destroy", "rsst_batch_plan", "rsst_adjoint_step", "rsst_adjoint_step_u1",
+                     "rsst_step_out"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -177,6 +180,11 @@ def rsst_step(h, U, dt_fixed: float = 0.0, stream=None):
     _check(lib().rsst_step(h, _ptr(U), float(dt_fixed), _stream(stream)), "rsst_step")
 
 
+def rsst_step_out(h, U, U1, Unext, dt_fixed: float = 0.0, stream=None):
+    _check(lib().rsst_step_out(h, _ptr(U), _ptr(U1), _ptr(Unext), float(dt_fixed), _stream(stream)),
+           "rsst_step_out")
+
+
 def rsst_step_noalloc(cfg: rsst_config, U, dt_fixed: float = 0.0, flags=None, stream=None):
     """One step with no allocation (fixed library scratch); flags: None or a
     one-element int32/uint32 device tensor that receives the step's flags."""
@@ -227,6 +235,11 @@ def rsst_adjoint_step(h, U, lam, dt: float, dJdxi, stream=None):
            "rsst_adjoint_step")
 
 
+def rsst_adjoint_step_u1(h, U, U1, lam, dt: float, dJdxi, stream=None):
+    _check(lib().rsst_adjoint_step_u1(h, _ptr(U), _ptr(U1), _ptr(lam), float(dt), _ptr(dJdxi), _stream(stream)),
+           "rsst_adjoint_step_u1")
+
+
 def rsst_version() -> str:
     return lib().rsst_version().decode()
 
@@ -264,10 +277,19 @@ class Solver:
     def diag(self, U, stream=None):
         return rsst_diag(self.h, U, stream)
 
-    def adjoint_step(self, U, lam, dt, dJdxi, stream=None):
+    def step_out(self, U, U1, Unext, dt_fixed=0.0, stream=None):
+        """One step out of place: U1 = U + dt R(U), Unext = the stepped state
+        (U unchanged; same bits as step)."""
+        rsst_step_out(self.h, U, U1, Unext, dt_fixed, stream)
+
+    def adjoint_step(self, U, lam, dt, dJdxi, stream=None, U1=None):
         """lam <- (dU'/dU)^T lam for the fixed-dt step from U; dJdxi (a
-        1-element float64 CUDA tensor) += (dU'/dxi)^T lam."""
-        rsst_adjoint_step(self.h, U, lam, dt, dJdxi, stream)
+        1-element float64 CUDA tensor) += (dU'/dxi)^T lam.  U1: the step's
+        stage value as step_out left it (else recomputed)."""
+        if U1 is None:
+            rsst_adjoint_step(self.h, U, lam, dt, dJdxi, stream)
+        else:
+            rsst_adjoint_step_u1(self.h, U, U1, lam, dt, dJdxi, stream)
 
     def poll(self):
         return rsst_poll(self.h)

@@ -13,7 +13,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "librsst.so")
-SOURCES = ["csrc/rsst_kernels.hip", "csrc/rsst_batch.hip", "csrc/rsst_adjoint.hip", "csrc/rsst_api.hip"]
+SOURCES = ["csrc/rsst_kernels.hip", "csrc/rsst_batch.hip", "csrc/rsst_adjoint.hip", "csrc/rsst_adjoint_tile.hip",
+           "csrc/rsst_api.hip"]
 # the stage kernels, one object per dimension, storage type and addressing
 # (big: 3D states of 2 GiB or more)
 STAGE_UNITS = [(nd, st, 0) for nd in (3, 2, 1) for st in ("double", "float")] + \

@@ -18,7 +18,9 @@ struct AdjointPlan {
   double* work;  // adjoint_workspace_doubles(ndim, ncell) doubles
 };
 
-size_t adjoint_workspace_doubles(int ndim, long long ncell);
+// Doubles of adjoint workspace for a grid of ncell cells, n[0..ndim-1] per
+// axis.
+size_t adjoint_workspace_doubles(int ndim, const int n[3], long long ncell);
 
 // lam <- (dU'/dU)^T lam for the step U -> U' of fixed dt, whose stage value
 // U1 = U + dt R(U) is given; dJdxi += (dU'/dxi)^T lam (device scalar).

@@ -18,8 +18,9 @@
 // cell state (normal momentum negated), so the wall face's outer state is
 // S of the inner face state and its cotangent returns through S.
 //
-// The VJP runs as three passes, each writing only its own cells, so the
-// result is deterministic (no atomics):
+// On a 1D or 3D grid the VJP runs as the three passes below (a 2D grid
+// takes the tiled form of the same passes, rsst_adjoint_tile.hip), each
+// writing only its own cells, so the result is deterministic (no atomics):
 //   A2 cell   fluxes G = 2 Fhat at the cell's two faces of every axis (a
 //             face shared by two cells is formed by both, the same bits),
 //             increments Delta, reverse of correction + gravity:
@@ -36,44 +37,11 @@
 #include <cstdint>
 
 #include "rsst_adjoint.h"
-#include "rsst_device.h"
+#include "rsst_adjoint_ops.h"
 
 #pragma clang fp contract(off)
 
 namespace rsstk {
-
-constexpr int kAdjThreads = 256;
-
-struct AdjArgs {
-  int ndim, nv;
-  int n[3];
-  int refl_lo[3], refl_hi[3];
-  long long ncell;
-  long long stride[3];  // cells between neighbours along each axis
-  double inv_dx[3];
-  double gamma, gm1, inv_gm1, inv_xi, f, dfdxi;
-  double g[3];
-  const double* V;   // primal state [nv][ncell]
-  const double* W;   // cotangent of R [nv][ncell]
-  double* out;       // J_R^T W [nv][ncell]
-  double* Db;        // [nv][ncell]
-  double* Pb;        // [ndim][nv][ncell]
-  double* Mb;        // [ndim][nv][ncell]
-  double* xpart;     // [2][nblock] partial sums of xi_bar
-  int nblock;
-  // what the last pass does with its result r = J_R^T W (per element):
-  // 0: out = r; 1: mu = (lam + dt r)/2; 2: lam = lam/2 + mu + dt r
-  int post;
-  double* lam;
-  double* mu;
-  double dt;
-  // the second VJP's last pass also folds the xi partials of both VJPs into
-  // dJdxi (its workgroup 0, after its own cells)
-  const double* xp1;
-  const double* xp2;
-  int xm;
-  double* dJdxi;
-};
 
 __device__ __forceinline__ void cell_coords(const AdjArgs& A, long long c, int x[3]) {
   x[0] = (int)(c % A.n[0]);
@@ -114,178 +82,7 @@ __device__ __forceinline__ void load_nb(const AdjArgs& A, const double* U, long 
   if (neg) u[1 + d] = -u[1 + d];
 }
 
-// ---------------------------------------------------------------- reverse
-
-// dh/dl, dh/dr of the MC half slope h = MC(l, r)/2 with the tie rule above.
-__device__ __forceinline__ void mc_half_partials(double l, double r, double& dl, double& dr) {
-  dl = 0.0;
-  dr = 0.0;
-  if (l * r <= 0.0) return;
-  const double q1 = fabs(l + r) * 0.5, q2 = 2.0 * fabs(l), q3 = 2.0 * fabs(r);
-  if (q1 <= q2 && q1 <= q3) {
-    dl = 0.25;
-    dr = 0.25;
-  } else if (q2 <= q3) {
-    dl = 1.0;
-  } else {
-    dr = 1.0;
-  }
-}
-
-// Pulls back through the primitives of a state u: the cotangents of the
-// velocity vb and the pressure Pb are added into ub (V = m/rho,
-// P = (gamma-1)(E - |m|^2/(2 rho))).
-template <int NDIM>
-__device__ __forceinline__ void prim_pullback(const double (&u)[NDIM + 2], const double (&v)[NDIM], double ri,
-                                              double v2, const double (&vb)[NDIM], double Pb, double gm1,
-                                              double (&ub)[NDIM + 2]) {
-  constexpr int NV = NDIM + 2;
-#pragma unroll
-  for (int e = 0; e < NDIM; ++e) {
-    ub[1 + e] += vb[e] * ri - gm1 * v[e] * Pb;
-    ub[0] -= vb[e] * v[e] * ri;
-  }
-  ub[NV - 1] += gm1 * Pb;
-  ub[0] += gm1 * 0.5 * v2 * Pb;
-}
-
-// ub += J_F(u)^T Gb for the Euler flux along D, plus the pull-back of a
-// cotangent cb of c_tot = |V| + a/xi (xib collects dc/dxi cb).
-template <int NDIM, int D>
-__device__ __forceinline__ void flux_ctot_vjp(const double (&u)[NDIM + 2], const double (&Gb)[NDIM + 2], double cb,
-                                              double gamma, double gm1, double inv_xi, double (&ub)[NDIM + 2],
-                                              double& xib) {
-  constexpr int NV = NDIM + 2;
-  const double rho = u[0], ri = 1.0 / rho;
-  double v[NDIM], v2 = 0.0;
-#pragma unroll
-  for (int e = 0; e < NDIM; ++e) {
-    v[e] = u[1 + e] * ri;
-    v2 += v[e] * v[e];
-  }
-  const double P = gm1 * (u[NV - 1] - 0.5 * rho * v2);
-  double vb[NDIM];
-#pragma unroll
-  for (int e = 0; e < NDIM; ++e) vb[e] = 0.0;
-  double Pb = 0.0;
-  // F = (m_D, m_e v_D + P delta_eD, (E + P) v_D)
-  ub[1 + D] += Gb[0];
-#pragma unroll
-  for (int e = 0; e < NDIM; ++e) {
-    ub[1 + e] += Gb[1 + e] * v[D];
-    vb[D] += Gb[1 + e] * u[1 + e];
-  }
-  Pb += Gb[1 + D];
-  ub[NV - 1] += Gb[NV - 1] * v[D];
-  Pb += Gb[NV - 1] * v[D];
-  vb[D] += Gb[NV - 1] * (u[NV - 1] + P);
-  // c_tot = |V| + a / xi
-  if (cb != 0.0) {
-    const double vabs = sqrt(v2);
-    const double a = sqrt(gamma * P * ri);
-    if (vabs > 0.0) {
-#pragma unroll
-      for (int e = 0; e < NDIM; ++e) vb[e] += cb * v[e] / vabs;
-    }
-    const double ab = cb * inv_xi;
-    xib += -cb * a * inv_xi * inv_xi;
-    // a = sqrt(gamma P / rho): da = gamma/(2 a rho) dP - a/(2 rho) drho
-    Pb += ab * gamma / (2.0 * a * rho);
-    ub[0] -= ab * a / (2.0 * rho);
-  }
-  prim_pullback<NDIM>(u, v, ri, v2, vb, Pb, gm1, ub);
-}
-
-// Reverse of the corrected rate with gravity at one cell: given Rb, sets
-// Db = (dR/dDelta)^T Rb, adds (dR/du)^T Rb into ub and returns dR/df . Rb.
-template <int NDIM, int FORM>
-__device__ __forceinline__ double rate_vjp(const double (&u)[NDIM + 2], const double (&Dl)[NDIM + 2],
-                                           const double (&Rb)[NDIM + 2], const AdjArgs& A,
-                                           double (&Db)[NDIM + 2], double (&ub)[NDIM + 2]) {
-  constexpr int NV = NDIM + 2;
-  const double rho = u[0], ri = 1.0 / rho;
-  double v[NDIM], v2 = 0.0, vdm = 0.0;
-#pragma unroll
-  for (int e = 0; e < NDIM; ++e) {
-    v[e] = u[1 + e] * ri;
-    v2 += v[e] * v[e];
-    vdm += v[e] * Dl[1 + e];
-  }
-  const double P = A.gm1 * (u[NV - 1] - 0.5 * rho * v2);
-  const double H = (u[NV - 1] + P) * ri;
-  const double dP = A.gm1 * (0.5 * v2 * Dl[0] - vdm + Dl[NV - 1]);
-#pragma unroll
-  for (int q = 0; q < NV; ++q) Db[q] = Rb[q];
-  double vb[NDIM];
-#pragma unroll
-  for (int e = 0; e < NDIM; ++e) vb[e] = 0.0;
-  double Pb = 0.0, rhob = 0.0, Hb = 0.0, dPb = 0.0, fb = 0.0;
-  if constexpr (FORM == kPVS || FORM == kPMS || FORM == kDVS || FORM == kDMS) {
-    constexpr bool VEL = (FORM == kPVS || FORM == kDVS);  // correction vector (1, V, H)
-    double s, sb;
-    if constexpr (FORM == kPVS || FORM == kPMS) s = A.f * dP * rho / (A.gamma * P);
-    else s = A.f * Dl[0];
-    if constexpr (VEL) {
-      sb = -Rb[0] - H * Rb[NV - 1];
-#pragma unroll
-      for (int e = 0; e < NDIM; ++e) {
-        sb -= v[e] * Rb[1 + e];
-        vb[e] -= s * Rb[1 + e];
-      }
-      Hb = -s * Rb[NV - 1];
-    } else {  // (1, 0, H - |V|^2)
-      sb = -Rb[0] - (H - v2) * Rb[NV - 1];
-      Hb = -s * Rb[NV - 1];
-#pragma unroll
-      for (int e = 0; e < NDIM; ++e) vb[e] += 2.0 * s * Rb[NV - 1] * v[e];
-    }
-    if constexpr (FORM == kPVS || FORM == kPMS) {
-      const double k = rho / (A.gamma * P);
-      dPb = sb * A.f * k;
-      fb = sb * dP * k;
-      rhob += sb * A.f * dP / (A.gamma * P);
-      Pb -= sb * s / P;
-    } else {
-      Db[0] += A.f * sb;
-      fb = Dl[0] * sb;
-    }
-  } else if constexpr (FORM == kPD) {
-    dPb = -A.f * A.inv_gm1 * Rb[NV - 1];
-    fb = -A.inv_gm1 * dP * Rb[NV - 1];
-  }
-  if (dPb != 0.0) {
-    // dP = (gamma-1)(|V|^2/2 Delta rho - V.Delta m + Delta E)
-    Db[0] += A.gm1 * 0.5 * v2 * dPb;
-#pragma unroll
-    for (int e = 0; e < NDIM; ++e) {
-      Db[1 + e] -= A.gm1 * v[e] * dPb;
-      vb[e] += A.gm1 * (v[e] * Dl[0] - Dl[1 + e]) * dPb;
-    }
-    Db[NV - 1] += A.gm1 * dPb;
-  }
-  // H = (E + P) / rho
-  ub[NV - 1] += Hb * ri;
-  Pb += Hb * ri;
-  rhob -= Hb * H * ri;
-  // gravity: R_m += rho g, R_E += m.g
-#pragma unroll
-  for (int e = 0; e < NDIM; ++e) {
-    rhob += A.g[e] * Rb[1 + e];
-    ub[1 + e] += A.g[e] * Rb[NV - 1];
-  }
-  ub[0] += rhob;
-  prim_pullback<NDIM>(u, v, ri, v2, vb, Pb, A.gm1, ub);
-  return fb;
-}
-
 // ---------------------------------------------------------------- passes
-
-template <int NDIM>
-__device__ __forceinline__ void half_slope(const double (&um)[NDIM + 2], const double (&u0)[NDIM + 2],
-                                           const double (&up)[NDIM + 2], double (&h)[NDIM + 2]) {
-#pragma unroll
-  for (int v = 0; v < NDIM + 2; ++v) h[v] = mc_half(u0[v] - um[v], up[v] - u0[v]);
-}
 
 template <int NDIM, int D>
 __device__ __forceinline__ void face_pair(const AdjArgs& A, const Consts& K, long long c, const int x[3],
@@ -320,11 +117,6 @@ __device__ __forceinline__ void wall_lo_pair(const AdjArgs& A, const Consts& K, 
   half_slope<NDIM>(um, u0, up, h0);
   make_face<NDIM, D>(u0, h0, false, K, R);
   L = mirror<NDIM, D>(R);
-}
-
-template <int NDIM>
-__device__ __forceinline__ Consts adj_consts(const AdjArgs& A) {
-  return Consts{A.gamma, A.gm1, A.inv_gm1, A.inv_xi, A.f};
 }
 
 __device__ __forceinline__ void block_partial(double v, double* out) {
@@ -405,31 +197,6 @@ __global__ void __launch_bounds__(kAdjThreads) adj_cell_kernel(AdjArgs A) {
     }
   }
   block_partial(xib, A.xpart);
-}
-
-// Reverse of G = F(L) + F(R) - alpha (R - L): Lb, Rb and the xi part.
-template <int NDIM, int D>
-__device__ __forceinline__ void llf_vjp(const Face<NDIM + 2>& L, const Face<NDIM + 2>& R, const double (&Gb)[NDIM + 2],
-                                        const AdjArgs& A, double (&Lb)[NDIM + 2], double (&Rbar)[NDIM + 2],
-                                        double& xib) {
-  constexpr int NV = NDIM + 2;
-  const bool left = L.c >= R.c;
-  const double alpha = left ? L.c : R.c;
-  double ab = 0.0;
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    Lb[v] = alpha * Gb[v];
-    Rbar[v] = -alpha * Gb[v];
-    ab -= Gb[v] * (R.u[v] - L.u[v]);
-  }
-  flux_ctot_vjp<NDIM, D>(L.u, Gb, left ? ab : 0.0, A.gamma, A.gm1, A.inv_xi, Lb, xib);
-  flux_ctot_vjp<NDIM, D>(R.u, Gb, left ? 0.0 : ab, A.gamma, A.gm1, A.inv_xi, Rbar, xib);
-}
-
-template <int NDIM, int D>
-__device__ __forceinline__ void mirror_add(double (&dst)[NDIM + 2], const double (&src)[NDIM + 2]) {
-#pragma unroll
-  for (int v = 0; v < NDIM + 2; ++v) dst[v] += (v == 1 + D) ? -src[v] : src[v];
 }
 
 template <int NDIM, int D>
@@ -600,32 +367,6 @@ __device__ __forceinline__ void gather_cell(const AdjArgs& A, long long c) {
   }
 }
 
-// dJdxi += dt/2 (sum of the U1 partials) + dt (sum of the U partials), in a
-// fixed order, by one workgroup (every thread of it calls this).
-__device__ __forceinline__ void xi_reduce(const double* p1, const double* p2, int m, double dt, double* dJdxi) {
-  __shared__ double red[2][kAdjThreads / 64];
-  double s1 = 0.0, s2 = 0.0;
-  for (int q = threadIdx.x; q < m; q += kAdjThreads) {
-    s1 += p1[q];
-    s2 += p2[q];
-  }
-  s1 = wave_sum(s1);
-  s2 = wave_sum(s2);
-  if ((threadIdx.x & 63) == 0) {
-    red[0][threadIdx.x >> 6] = s1;
-    red[1][threadIdx.x >> 6] = s2;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double a = 0.0, b = 0.0;
-    for (int q = 0; q < kAdjThreads / 64; ++q) {
-      a += red[0][q];
-      b += red[1][q];
-    }
-    *dJdxi += 0.5 * dt * a + dt * b;
-  }
-}
-
 // The last pass of a VJP; in the second VJP its workgroup 0 also folds the
 // xi partials of both VJPs (complete: their passes ended before this one
 // began) into dJdxi, after its own cells.
@@ -633,7 +374,7 @@ template <int NDIM>
 __global__ void __launch_bounds__(kAdjThreads) adj_gather_kernel(AdjArgs A) {
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (c < A.ncell) gather_cell<NDIM>(A, c);
-  if (A.post == 2 && blockIdx.x == 0) xi_reduce(A.xp1, A.xp2, A.xm, A.dt, A.dJdxi);
+  if (A.post == 2 && blockIdx.x == 0) xi_reduce<kAdjThreads>(A.xp1, A.xp2, A.xm, A.dt, A.dJdxi);
 }
 
 template <int NDIM>
@@ -659,8 +400,12 @@ static hipError_t vjp_launch(AdjArgs A, int form, hipStream_t s) {
   return hipGetLastError();
 }
 
-size_t adjoint_workspace_doubles(int ndim, long long ncell) {
+size_t adjoint_workspace_doubles(int ndim, const int n[3], long long ncell) {
   const int nv = ndim + 2;
+  if (ndim == 2) {
+    // mu, two partial arrays of one sum per tile
+    return (size_t)nv * ncell + 2 * (size_t)tile2_nblock(n);
+  }
   const long long nblock = (ncell + kAdjThreads - 1) / kAdjThreads;
   // Pb, Mb: ndim fields each; Db, a/b, mu: one each; 4 partial arrays
   return (size_t)nv * ncell * (2 * ndim + 3) + 4 * (size_t)nblock;
@@ -692,6 +437,33 @@ hipError_t launch_adjoint_step(const AdjointPlan& p, const double* U, const doub
   A.inv_xi = 1.0 / p.xi;
   A.f = 1.0 - 1.0 / (p.xi * p.xi);
   A.dfdxi = 2.0 / (p.xi * p.xi * p.xi);
+  A.lam = lam;
+  A.dt = dt;
+  A.dJdxi = dJdxi;
+  if (ndim == 2) {
+    // one tiled launch per VJP; each leaves one partial sum of xi_bar per
+    // tile, and a one-workgroup launch after the second folds both sets
+    const int nt = tile2_nblock(p.n);
+    double* const part1 = w + nf;
+    double* const part2 = part1 + nt;
+    A.mu = w;
+    A.nblock = nt;
+    A.xp1 = part1;
+    A.xp2 = part2;
+    A.V = U1;
+    A.W = lam;
+    A.xpart = part1;
+    A.post = 1;
+    hipError_t e = launch_vjp_tile2(A, p.form, s);
+    if (e != hipSuccess) return e;
+    A.V = U;
+    A.W = A.mu;
+    A.xpart = part2;
+    A.post = 2;
+    e = launch_vjp_tile2(A, p.form, s);
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
+  }
   A.Pb = w;
   A.Mb = A.Pb + ndim * nf;
   A.Db = A.Mb + ndim * nf;
@@ -700,26 +472,19 @@ hipError_t launch_adjoint_step(const AdjointPlan& p, const double* U, const doub
   double* part1 = mu + nf;
   double* part2 = part1 + 2 * nblock;
   A.nblock = nblock;
-  A.lam = lam;
   A.mu = mu;
-  A.dt = dt;
   // each VJP leaves partials of the f part then the alpha part (2 nblock
   // each); the second VJP's last pass folds both sets into dJdxi
   A.xp1 = part1;
   A.xp2 = part2;
   A.xm = 2 * nblock;
-  A.dJdxi = dJdxi;
   auto vjp = [&](const double* V, const double* Wc, double* out, double* part, int post) {
     A.V = V;
     A.W = Wc;
     A.out = out;
     A.xpart = part;
     A.post = post;
-    switch (ndim) {
-      case 1: return vjp_launch<1>(A, p.form, s);
-      case 2: return vjp_launch<2>(A, p.form, s);
-      default: return vjp_launch<3>(A, p.form, s);
-    }
+    return ndim == 1 ? vjp_launch<1>(A, p.form, s) : vjp_launch<3>(A, p.form, s);
   };
   // (a, s1) = VJP(U1, lam) with mu = (lam + dt a)/2 formed by its last pass
   hipError_t e = vjp(U1, lam, ab, part1, 1);

@@ -238,7 +238,7 @@ int rsst_init(const rsst_config* cfg, void* stream, rsst_handle* out) {
   }
   h->adj_work = nullptr;
   if (cfg->flags & RSST_WITH_ADJOINT) {
-    const size_t nd = rsstk::adjoint_workspace_doubles(cfg->ndim, h->ncell);
+    const size_t nd = rsstk::adjoint_workspace_doubles(cfg->ndim, cfg->n, h->ncell);
     if (hipMalloc((void**)&h->adj_work, nd * sizeof(double)) != hipSuccess) {
       h->adj_work = nullptr;
       rsst_destroy(h);
@@ -296,6 +296,30 @@ int rsst_step(rsst_handle h, void* U, double dt_fixed, void* stream) {
   int st = rsst_stage(h, U, 1, dt_fixed, stream);
   if (st != RSST_OK) return st;
   return rsst_stage(h, U, 2, dt_fixed, stream);
+}
+
+int rsst_step_out(rsst_handle h, const void* U, void* U1, void* Unext, double dt_fixed, void* stream) {
+  if (!h || !U || !U1 || !Unext || !std::isfinite(dt_fixed)) return RSST_E_ARG;
+  if (U1 == U || Unext == U || U1 == Unext) return RSST_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  StageArgs a = h->args;
+  a.dt_fixed = dt_fixed > 0.0 ? dt_fixed : 0.0;
+  if (dt_fixed <= 0.0 && !h->primed) {
+    if (rsstk::launch_prime(h->args, U, 0.0, 0, s) != hipSuccess) return RSST_E_DEVICE;
+    h->primed = true;
+  }
+  // the two stages of rsst_step with the caller's buffers in place of the
+  // stage buffer and of U
+  a.uin = U;
+  a.un = nullptr;
+  a.uout = U1;
+  if (rsstk::launch_stage(a, 1, s) != hipSuccess) return RSST_E_DEVICE;
+  a.uin = U1;
+  a.un = U;
+  a.uout = Unext;
+  if (rsstk::launch_stage(a, 2, s) != hipSuccess) return RSST_E_DEVICE;
+  h->primed = true;
+  return RSST_OK;
 }
 
 int rsst_steps(rsst_handle h, void* U, int nsteps, double dt_fixed, void* stream) {
@@ -388,17 +412,8 @@ int rsst_destroy(rsst_handle h) {
   return RSST_OK;
 }
 
-int rsst_adjoint_step(rsst_handle h, const void* U, double* lam, double dt, double* dJdxi, void* stream) {
-  if (!h || !U || !lam || !dJdxi || !(dt > 0.0) || !std::isfinite(dt)) return RSST_E_ARG;
-  if (!h->adj_work) return RSST_E_UNSUPPORTED;
-  hipStream_t s = (hipStream_t)stream;
-  // U1 = U + dt R(U), the same stage-1 kernel as the forward step
-  StageArgs a = h->args;
-  a.dt_fixed = dt;
-  a.uin = U;
-  a.un = nullptr;
-  a.uout = h->u1;
-  if (rsstk::launch_stage(a, 1, s) != hipSuccess) return RSST_E_DEVICE;
+static int adjoint_pullback(rsst_handle h, const void* U, const void* U1, double* lam, double dt, double* dJdxi,
+                            hipStream_t s) {
   const rsst_config& c = h->cfg;
   rsstk::AdjointPlan p{};
   p.ndim = c.ndim;
@@ -414,7 +429,28 @@ int rsst_adjoint_step(rsst_handle h, const void* U, double* lam, double dt, doub
   p.form = c.form;
   p.ncell = h->ncell;
   p.work = h->adj_work;
-  return check(rsstk::launch_adjoint_step(p, (const double*)U, (const double*)h->u1, lam, dt, dJdxi, s));
+  return check(rsstk::launch_adjoint_step(p, (const double*)U, (const double*)U1, lam, dt, dJdxi, s));
+}
+
+int rsst_adjoint_step(rsst_handle h, const void* U, double* lam, double dt, double* dJdxi, void* stream) {
+  if (!h || !U || !lam || !dJdxi || !(dt > 0.0) || !std::isfinite(dt)) return RSST_E_ARG;
+  if (!h->adj_work) return RSST_E_UNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  // U1 = U + dt R(U), the same stage-1 kernel as the forward step
+  StageArgs a = h->args;
+  a.dt_fixed = dt;
+  a.uin = U;
+  a.un = nullptr;
+  a.uout = h->u1;
+  if (rsstk::launch_stage(a, 1, s) != hipSuccess) return RSST_E_DEVICE;
+  return adjoint_pullback(h, U, h->u1, lam, dt, dJdxi, s);
+}
+
+int rsst_adjoint_step_u1(rsst_handle h, const void* U, const void* U1, double* lam, double dt, double* dJdxi,
+                         void* stream) {
+  if (!h || !U || !U1 || !lam || !dJdxi || !(dt > 0.0) || !std::isfinite(dt)) return RSST_E_ARG;
+  if (!h->adj_work) return RSST_E_UNSUPPORTED;
+  return adjoint_pullback(h, U, U1, lam, dt, dJdxi, (hipStream_t)stream);
 }
 
 int rsst_step_noalloc(const rsst_config* cfg, void* U, double dt_fixed, uint32_t* flags, void* stream) {

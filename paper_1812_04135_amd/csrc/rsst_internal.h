@@ -46,7 +46,7 @@ struct StageArgs {
   int nblk;          // stage-kernel workgroups (ntile_s * nchunk)
   const void* uin;   // stage input (halo reads)
   const void* un;    // stage 2: state at the start of the step (pointwise)
-  void* uout;        // stage output (stage 2: the same array as un, updated in place)
+  void* uout;        // stage output (stage 2: un itself for the in-place step, or another array)
   const double* bg;  // FP32 perturbation form: background [nv][nbg]
   int bg_axis;       // -1 uniform
   int nbg;

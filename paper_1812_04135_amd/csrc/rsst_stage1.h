@@ -85,7 +85,7 @@ __device__ __forceinline__ double stage_body1(const StageArgs& A, double* lds, d
   const Field32 uin = make_field<false>(A.uin, A.ncell, NV, SZ, plane);
   const Field32 unp = make_field<false>(A.un ? A.un : A.uin, A.ncell, NV, SZ, plane);
   // stage 2 writes the new state in place over the step-start state
-  const Field32 uout = STAGE == 2 ? unp : make_field<false>(A.uout, A.ncell, NV, SZ, plane);
+  const Field32 uout = make_field<false>(A.uout, A.ncell, NV, SZ, plane);
 
   double q0[NV];
   if constexpr (REG) {

@@ -150,7 +150,7 @@ __device__ __forceinline__ double stage_body3(const StageArgs& A, double* lds, i
   const FieldT<BIG> unp = make_field<BIG>(A.un ? A.un : A.uin, A.ncell, NV, SZ, plane);
   // stage 2 writes the new state in place over the step-start state (the
   // callers pass uout == un), so one field serves both
-  const FieldT<BIG> uout = STAGE == 2 ? unp : make_field<BIG>(A.uout, A.ncell, NV, SZ, plane);
+  const FieldT<BIG> uout = make_field<BIG>(A.uout, A.ncell, NV, SZ, plane);
 
   // y rows just outside the tile: columns, mirror flags, background rows and
   // hydrostatic levers

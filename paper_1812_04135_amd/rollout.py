@@ -6,7 +6,9 @@ Its backward pulls the incoming gradient back through every step with the
 hand-written adjoint (rsst_adjoint_step), giving dJ/dU0 and dJ/dxi.  The
 forward keeps only the states at every checkpoint_every-th step; the
 backward re-runs each segment forward from its checkpoint (device tensors
-only) and then runs the segment's adjoint steps in reverse.
+only, out of place, keeping each step's stage value U1 so that the adjoint
+does not recompute it) and then runs the segment's adjoint steps in
+reverse.
 
 The time step is frozen: dt is an input, not the CFL rule, so the gradient
 is that of the map U0 -> U_N at fixed dt.  The backward of a segment is
@@ -43,15 +45,15 @@ class RSSTRollout(torch.autograd.Function):
         return U
 
     @staticmethod
-    def _segment(solver, states, lam, dxi, dt, m):
-        """Re-run m - 1 steps from states[0] into states[1..], then pull lam
-        back through the m steps (the states must already hold the
-        checkpoint in states[0])."""
+    def _segment(solver, states, stage1, lam, dxi, dt, m):
+        """Re-run m - 1 steps from states[0] into states[1..], keeping each
+        step's stage value in stage1[..], then pull lam back through the m
+        steps (the last one recomputes its stage value; states[0] must
+        already hold the checkpoint)."""
         for i in range(1, m):
-            states[i].copy_(states[i - 1])
-            solver.step(states[i], dt)
+            solver.step_out(states[i - 1], stage1[i - 1], states[i], dt)
         for n in reversed(range(m)):
-            solver.adjoint_step(states[n], lam, dt, dxi)
+            solver.adjoint_step(states[n], lam, dt, dxi, U1=stage1[n] if n < m - 1 else None)
 
     @staticmethod
     def backward(ctx, gU):
@@ -60,25 +62,26 @@ class RSSTRollout(torch.autograd.Function):
         dxi = torch.zeros(1, dtype=torch.float64, device=lam.device)
         nseg = len(ctx.ckpts)
         states = [torch.empty_like(lam) for _ in range(min(K, nsteps))]
+        stage1 = [torch.empty_like(lam) for _ in range(min(K, nsteps) - 1)]
         graphs = {}
         for seg in reversed(range(nseg)):
             n0, n1 = seg * K, min((seg + 1) * K, nsteps)
             m = n1 - n0
             states[0].copy_(ctx.ckpts[seg])
             if not ctx.use_graph or nseg < 3:
-                RSSTRollout._segment(solver, states, lam, dxi, dt, m)
+                RSSTRollout._segment(solver, states, stage1, lam, dxi, dt, m)
                 continue
             if m not in graphs:
                 # first segment of this length runs eagerly (it also sets up
                 # the kernels), later ones replay a HIP graph of the same
                 # launches: forward re-run and adjoint steps
-                RSSTRollout._segment(solver, states, lam, dxi, dt, m)
+                RSSTRollout._segment(solver, states, stage1, lam, dxi, dt, m)
                 g = torch.cuda.CUDAGraph()
                 lam_in = lam.clone()
                 dxi_in = dxi.clone()
                 torch.cuda.synchronize()
                 with torch.cuda.graph(g):
-                    RSSTRollout._segment(solver, states, lam, dxi, dt, m)
+                    RSSTRollout._segment(solver, states, stage1, lam, dxi, dt, m)
                 # capturing does not run the work: restore the cotangents
                 lam.copy_(lam_in)
                 dxi.copy_(dxi_in)

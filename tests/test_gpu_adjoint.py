@@ -38,6 +38,10 @@ CASES = [
     (2, [17, 13], "dms", ["reflect", "periodic"], [0.3, 0.0], 6.0),
     (2, [16, 12], "pd", ["periodic", "reflect"], [0.0, -0.5], 2.5),
     (2, [16, 12], "euler", ["reflect", "reflect"], [0.0, -0.5], 1.0),
+    # several 16 x 16 tiles of the 2D VJP, ragged on both axes
+    (2, [41, 35], "pvs", ["reflect", "periodic"], [0.2, 0.0], 5.0),
+    (2, [40, 50], "pd", ["periodic", "reflect"], [0.0, -0.4], 3.0),
+    (2, [70, 33], "dms", ["reflect", "reflect"], [0.1, -0.3], 7.0),
     (3, [12, 10, 8], "pvs", ["periodic", "periodic", "reflect"], [0.0, 0.0, -0.5], 8.0),
     (3, [9, 8, 7], "pd", ["reflect", "reflect", "reflect"], [0.1, 0.0, -0.4], 3.0),
 ]
@@ -267,3 +271,58 @@ def test_rollout_graph_replays_equal_eager(K):
         res.append((U.grad.cpu().numpy(), float(xi.grad)))
     for g, x in res[1:]:
         assert np.array_equal(g, res[0][0]) and x == res[0][1]
+
+
+STEP_OUT_CASES = [
+    (1, [40], "pvs", ["reflect"], [-0.3], 3.0),
+    (2, [41, 35], "pms", ["periodic", "reflect"], [0.0, -0.4], 5.0),
+    (3, [20, 14, 9], "pd", ["periodic", "periodic", "reflect"], [0.0, 0.0, -0.5], 4.0),
+]
+
+
+@pytest.mark.parametrize("case", STEP_OUT_CASES, ids=[_ids(c) for c in STEP_OUT_CASES])
+@pytest.mark.parametrize("fixed", [True, False], ids=["fixed-dt", "cfl-dt"])
+def test_step_out_matches_step(case, fixed):
+    """rsst_step_out leaves in Unext the bits rsst_step leaves in U, U is
+    untouched, t advances the same way; and the adjoint step given that U1
+    equals the one that recomputes it, bit for bit."""
+    ndim, n, form, bc, g, xi = case
+    cfg, U0 = W.random_state(ndim, n, seed_k=740 + sum(n), xi=xi, form=form, bc_lo=bc, g=g)
+    dt = 0.5 * oracle.cfl_dt(cfg, U0) if fixed else 0.0
+    a, b = R.Solver(cfg, adjoint=True), R.Solver(cfg, adjoint=True)
+    Ua = torch.from_numpy(np.ascontiguousarray(U0)).cuda()
+    Ub = Ua.clone()
+    U1 = torch.empty_like(Ua)
+    Un = torch.empty_like(Ua)
+    for _ in range(3):
+        Ub_before = Ub.clone()
+        a.step(Ua, dt)
+        b.step_out(Ub, U1, Un, dt)
+        assert torch.equal(Ub, Ub_before)
+        assert torch.equal(Ua, Un)
+        Ub.copy_(Un)
+    assert a.time() == b.time()
+    if fixed:
+        lam_a = torch.from_numpy(np.random.default_rng(W.seed(74)).standard_normal(U0.shape)).cuda()
+        lam_b = lam_a.clone()
+        da = torch.zeros(1, dtype=torch.float64, device="cuda")
+        db = torch.zeros(1, dtype=torch.float64, device="cuda")
+        b.step_out(Ub, U1, Un, dt)
+        a.adjoint_step(Ub, lam_a, dt, da)
+        b.adjoint_step(Ub, lam_b, dt, db, U1=U1)
+        torch.cuda.synchronize()
+        assert torch.equal(lam_a, lam_b) and torch.equal(da, db)
+    a.close()
+    b.close()
+
+
+def test_step_out_rejects_aliased_buffers():
+    cfg, U0 = W.random_state(2, [16, 16], seed_k=750, xi=3.0, form="pvs", bc_lo=["periodic", "periodic"],
+                             g=[0.0, 0.0])
+    s = R.Solver(cfg)
+    U = torch.from_numpy(np.ascontiguousarray(U0)).cuda()
+    other = torch.empty_like(U)
+    for U1, Un in ((U, other), (other, U), (other, other)):
+        with pytest.raises(R.RsstError):
+            s.step_out(U, U1, Un, 1e-3)
+    s.close()
