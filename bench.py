@@ -357,8 +357,10 @@ def adjoint_roofline(version, step_ms):
 
 def bench_adjoint(R, W, np, torch, stream, args):
     """Gradient of the final kinetic energy of the 256^2 bubble (xi = 10,
-    400 fixed-dt steps, checkpoints every 20) w.r.t. the initial density
-    field and xi, with central differences on 32 directions as its error."""
+    400 fixed-dt steps) w.r.t. the initial density field and xi, with the
+    trajectory kept in HBM (and, for comparison, checkpoints every 20 steps
+    with the segments re-run), with central differences on 32 directions as
+    its error."""
     from paper_1812_04135_amd.rollout import kinetic_energy, rollout
     cfg, U0np, meta = W.adjoint2d(n=256, ndir=32)
     nsteps, K = args.adjoint_steps, 20
@@ -392,23 +394,33 @@ def bench_adjoint(R, W, np, torch, stream, args):
     b.record(stream)
     b.synchronize()
     fwd_ms = a.elapsed_time(b)
-    # one untimed forward + backward first (loads the adjoint kernels; every
-    # backward captures its own segment graph, so that cost stays in the timing)
-    rw = rho0.clone().requires_grad_(True)
-    kinetic_energy(rollout(cons(rw), torch.tensor(cfg["xi"], dtype=torch.float64, requires_grad=True),
-                           cfg, 2 * K, dt, checkpoint_every=K), cfg).backward()
-    rho = rho0.clone().requires_grad_(True)
-    xi = torch.tensor(cfg["xi"], dtype=torch.float64, requires_grad=True)
-    UN = rollout(cons(rho), xi, cfg, nsteps, dt, checkpoint_every=K)
-    J = kinetic_energy(UN, cfg)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    J.backward()
-    e1.record(stream)
-    e1.synchronize()
-    bwd_ms = e0.elapsed_time(e1)
-    grad = rho.grad
+    # one untimed forward + backward of each kind first (loads the adjoint
+    # kernels; every checkpointed backward captures its own segment graphs,
+    # so that cost stays in its timing)
+    for k in (1, K):
+        rw = rho0.clone().requires_grad_(True)
+        kinetic_energy(rollout(cons(rw), torch.tensor(cfg["xi"], dtype=torch.float64, requires_grad=True),
+                               cfg, 2 * K, dt, checkpoint_every=k), cfg).backward()
+
+    def timed_backward(k):
+        rho = rho0.clone().requires_grad_(True)
+        xi = torch.tensor(cfg["xi"], dtype=torch.float64, requires_grad=True)
+        J = kinetic_energy(rollout(cons(rho), xi, cfg, nsteps, dt, checkpoint_every=k), cfg)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        J.backward()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1), rho.grad, xi.grad, J
+
+    # the whole trajectory kept in HBM ("auto" picks it: 2 x 400 states of
+    # 2 MiB), then checkpoints every K steps with the segments re-run
+    from paper_1812_04135_amd.rollout import trajectory_or_interval
+    kind = trajectory_or_interval(rho0, nsteps, "auto")
+    bwd_ms, grad, xi_grad, J = timed_backward("auto")
+    ck_ms, ck_grad, _, _ = timed_backward(K)
+    same_bits = bool(torch.equal(grad, ck_grad))
     h = 1e-6
     errs = []
     for q in range(meta["dirs"].shape[0]):
@@ -420,12 +432,17 @@ def bench_adjoint(R, W, np, torch, stream, args):
     errs = np.array(errs)
     adj_step_ms = bwd_ms / nsteps
     return {"adjoint_bubble256_fp64": {
-        "steps": nsteps, "checkpoint_every": K, "dt": dt, "J": float(J.detach()),
-        "dJ_dxi": float(xi.grad),
+        "steps": nsteps, "dt": dt, "J": float(J.detach()),
+        "dJ_dxi": float(xi_grad),
+        "backward_kept": "trajectory" if kind == 1 else f"checkpoints every {kind}",
+        "trajectory_bytes": 2 * nsteps * U.numel() * 8,
         "forward_ms": round(fwd_ms, 3), "backward_ms": round(bwd_ms, 3),
         "backward_ms_per_step": round(adj_step_ms, 5),
         "Gcell_updates_s": round(ncell * nsteps / (bwd_ms * 1e-3) / 1e9, 4),
         "backward_over_forward": round(bwd_ms / fwd_ms, 3),
+        "checkpoint_every": K, "backward_checkpointed_ms": round(ck_ms, 3),
+        "checkpointed_over_forward": round(ck_ms / fwd_ms, 3),
+        "checkpointed_same_dJdU0_bits": same_bits,
         "roofline": adjoint_roofline(R.rsst_version(), adj_step_ms),
         "fd_rel_err_median": float(np.median(errs)), "fd_rel_err_max": float(errs.max()),
         "fd_within_bar": bool(errs.max() <= 1e-4),

@@ -254,6 +254,20 @@ int rsst_adjoint_step(rsst_handle h, const void* U, double* lam, double dt, doub
 int rsst_adjoint_step_u1(rsst_handle h, const void* U, const void* U1, double* lam, double dt, double* dJdxi,
                          void* stream);
 
+/* The adjoint of nsteps fixed-dt steps over a trajectory kept by the caller:
+ * for n = nsteps-1 down to 0, the rsst_adjoint_step_u1 of the step from
+ * U_list[n] with stage value U1_list[n] (both as rsst_step_out left them),
+ * lam in place; then *dJdxi += the run's dJ/dxi.  U_list, U1_list: host
+ * arrays of nsteps device pointers (FP64); U1_list may be NULL (each stage
+ * value is then recomputed, as rsst_adjoint_step does).  lam leaves with the
+ * bits of nsteps rsst_adjoint_step_u1 calls; on a 2D grid dJ/dxi is summed
+ * per tile over the run and folded once at the end (the same value to
+ * rounding, not the same bits as per-call folds).  All launches on `stream`
+ * from this one call, so the device runs the steps back to back.
+ * RSST_E_ARG for a NULL entry, nsteps < 0 or dt <= 0. */
+int rsst_adjoint_run(rsst_handle h, const void* const* U_list, const void* const* U1_list, int nsteps, double* lam,
+                     double dt, double* dJdxi, void* stream);
+
 /* ---- Batched boxes ------------------------------------------------------
  * Many independent 2D boxes (each with its own size, xi, gravity, boundaries
  * and background) advanced together by one persistent kernel per run; the

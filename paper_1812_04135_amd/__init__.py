@@ -90,13 +90,15 @@ def lib():
         L.rsst_adjoint_step.argtypes = [vp, vp, vp, ctypes.c_double, vp, vp]
         L.rsst_adjoint_step_u1.argtypes = [vp, vp, vp, vp, ctypes.c_double, vp, vp]
         L.rsst_step_out.argtypes = [vp, vp, vp, vp, ctypes.c_double, vp]
+        L.rsst_adjoint_run.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int, vp,
+                                       ctypes.c_double, vp, vp]
         L.rsst_batch_plan.argtypes = [ctypes.POINTER(rsst_config), ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                       ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         for name in ("rsst_init", "rsst_prime", "rsst_step", "rsst_stage", "rsst_steps", "rsst_get_time",
                      "rsst_diag", "rsst_poll", "rsst_destroy", "rsst_batch_init", "rsst_batch_set_tiles",
                      "rsst_batch_get_tiles", "rsst_batch_run", "rsst_batch_times", "rsst_batch_poll",
                      "rsst_batch_destroy", "rsst_batch_plan", "rsst_adjoint_step", "rsst_adjoint_step_u1",
-                     "rsst_step_out"):
+                     "rsst_step_out", "rsst_adjoint_run"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -235,6 +237,20 @@ def rsst_adjoint_step(h, U, lam, dt: float, dJdxi, stream=None):
            "rsst_adjoint_step")
 
 
+def rsst_adjoint_run(h, U_list, U1_list, lam, dt: float, dJdxi, stream=None):
+    """Adjoint of len(U_list) steps over a kept trajectory (U1_list: the
+    stage values, or None to recompute them)."""
+    n = len(U_list)
+    us = (ctypes.c_void_p * max(n, 1))(*[_ptr(u) for u in U_list])
+    u1s = None
+    if U1_list is not None:
+        if len(U1_list) != n:
+            raise ValueError("rsst_adjoint_run: U1_list and U_list differ in length")
+        u1s = (ctypes.c_void_p * max(n, 1))(*[_ptr(u) for u in U1_list])
+    _check(lib().rsst_adjoint_run(h, us, u1s, n, _ptr(lam), float(dt), _ptr(dJdxi), _stream(stream)),
+           "rsst_adjoint_run")
+
+
 def rsst_adjoint_step_u1(h, U, U1, lam, dt: float, dJdxi, stream=None):
     _check(lib().rsst_adjoint_step_u1(h, _ptr(U), _ptr(U1), _ptr(lam), float(dt), _ptr(dJdxi), _stream(stream)),
            "rsst_adjoint_step_u1")
@@ -281,6 +297,11 @@ class Solver:
         """One step out of place: U1 = U + dt R(U), Unext = the stepped state
         (U unchanged; same bits as step)."""
         rsst_step_out(self.h, U, U1, Unext, dt_fixed, stream)
+
+    def adjoint_run(self, U_list, U1_list, lam, dt, dJdxi, stream=None):
+        """The adjoint of the steps U_list[n] -> U_list[n+1] (stage values
+        U1_list[n], or None), last step first, in one library call."""
+        rsst_adjoint_run(self.h, U_list, U1_list, lam, dt, dJdxi, stream)
 
     def adjoint_step(self, U, lam, dt, dJdxi, stream=None, U1=None):
         """lam <- (dU'/dU)^T lam for the fixed-dt step from U; dJdxi (a

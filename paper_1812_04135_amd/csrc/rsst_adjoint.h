@@ -22,9 +22,16 @@ struct AdjointPlan {
 // axis.
 size_t adjoint_workspace_doubles(int ndim, const int n[3], long long ncell);
 
+// The workspace from this offset on must be zero before the first adjoint
+// step (the run accumulator of a 2D grid; every run leaves it at zero).
+size_t adjoint_zeroed_offset(int ndim, const int n[3], long long ncell);
+
 // lam <- (dU'/dU)^T lam for the step U -> U' of fixed dt, whose stage value
 // U1 = U + dt R(U) is given; dJdxi += (dU'/dxi)^T lam (device scalar).
+// defer (2D grids): the dJ/dxi share goes into the per-tile run accumulator
+// instead, folded into dJdxi by launch_adjoint_xi_fold.
 hipError_t launch_adjoint_step(const AdjointPlan& p, const double* U, const double* U1, double* lam, double dt,
-                               double* dJdxi, hipStream_t s);
+                               double* dJdxi, bool defer, hipStream_t s);
+hipError_t launch_adjoint_xi_fold(const AdjointPlan& p, double* dJdxi, hipStream_t s);
 
 }  // namespace rsstk

@@ -403,16 +403,26 @@ static hipError_t vjp_launch(AdjArgs A, int form, hipStream_t s) {
 size_t adjoint_workspace_doubles(int ndim, const int n[3], long long ncell) {
   const int nv = ndim + 2;
   if (ndim == 2) {
-    // mu, two partial arrays of one sum per tile
-    return (size_t)nv * ncell + 2 * (size_t)tile2_nblock(n);
+    // mu; two partial arrays and the run accumulator, one value per tile
+    return (size_t)nv * ncell + 3 * (size_t)tile2_nblock(n);
   }
   const long long nblock = (ncell + kAdjThreads - 1) / kAdjThreads;
   // Pb, Mb: ndim fields each; Db, a/b, mu: one each; 4 partial arrays
   return (size_t)nv * ncell * (2 * ndim + 3) + 4 * (size_t)nblock;
 }
 
+size_t adjoint_zeroed_offset(int ndim, const int n[3], long long ncell) {
+  return ndim == 2 ? (size_t)(ndim + 2) * ncell + 2 * (size_t)tile2_nblock(n) : adjoint_workspace_doubles(ndim, n, ncell);
+}
+
+hipError_t launch_adjoint_xi_fold(const AdjointPlan& p, double* dJdxi, hipStream_t s) {
+  if (p.ndim != 2) return hipSuccess;
+  const int nt = tile2_nblock(p.n);
+  return launch_xi_acc_fold(p.work + adjoint_zeroed_offset(2, p.n, p.ncell), nt, dJdxi, s);
+}
+
 hipError_t launch_adjoint_step(const AdjointPlan& p, const double* U, const double* U1, double* lam, double dt,
-                               double* dJdxi, hipStream_t s) {
+                               double* dJdxi, bool defer, hipStream_t s) {
   const int ndim = p.ndim, nv = ndim + 2;
   const long long n = p.ncell, nf = (long long)nv * n;
   const int nblock = (int)((n + kAdjThreads - 1) / kAdjThreads);
@@ -450,6 +460,7 @@ hipError_t launch_adjoint_step(const AdjointPlan& p, const double* U, const doub
     A.nblock = nt;
     A.xp1 = part1;
     A.xp2 = part2;
+    A.xacc = defer ? part2 + nt : nullptr;
     A.V = U1;
     A.W = lam;
     A.xpart = part1;

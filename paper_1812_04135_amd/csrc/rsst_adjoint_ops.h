@@ -43,6 +43,10 @@ struct AdjArgs {
   const double* xp2;
   int xm;
   double* dJdxi;
+  // tiled 2D VJP, second VJP: when set, each tile adds its share of dJ/dxi
+  // (dt/2 its first-VJP partial + dt its own) into xacc[tile] instead of a
+  // fold into dJdxi (the caller folds the accumulator once, later)
+  double* xacc;
 };
 
 // ---------------------------------------------------------------- reverse
@@ -318,8 +322,11 @@ __device__ __forceinline__ void xi_reduce(const double* p1, const double* p2, in
 
 // The tiled 2D VJP (rsst_adjoint_tile.hip): one launch per VJP, one
 // workgroup and one partial sum of xi_bar per tile; after the second VJP
-// (post = 2) a one-workgroup launch folds both VJPs' partials into dJdxi.
+// (post = 2) a one-workgroup launch folds both VJPs' partials into dJdxi,
+// unless xacc is set.
 int tile2_nblock(const int n[3]);
 hipError_t launch_vjp_tile2(const AdjArgs& A, int form, hipStream_t s);
+// dJdxi += sum of acc[0..m) in a fixed order, then acc = 0 (one workgroup).
+hipError_t launch_xi_acc_fold(double* acc, int m, double* dJdxi, hipStream_t s);
 
 }  // namespace rsstk

@@ -131,6 +131,23 @@ __global__ void __launch_bounds__(kAdjThreads) adj_xi_fold_kernel(const double* 
   xi_reduce<kAdjThreads>(p1, p2, m, dt, dJdxi);
 }
 
+// dJ/dxi += sum of a run's per-tile accumulators, in a fixed order; the
+// accumulators are left at zero for the next run.
+__global__ void __launch_bounds__(kAdjThreads) adj_acc_fold_kernel(double* acc, int m, double* dJdxi) {
+  __shared__ double red[kAdjThreads / 64];
+  double s = 0.0;
+  for (int q = threadIdx.x; q < m; q += kAdjThreads) s += acc[q];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  for (int q = threadIdx.x; q < m; q += kAdjThreads) acc[q] = 0.0;
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < kAdjThreads / 64; ++q) t += red[q];
+    *dJdxi += t;
+  }
+}
+
 template <int TX, int TY>
 struct Tile2 {
   // U window: positions (x0-4 .. x0+TX+3, y0-4 .. y0+TY+3), [v][py][px]
@@ -358,7 +375,9 @@ __global__ void __launch_bounds__(NT) adj_tile2_kernel(AdjArgs A) {
   if (tid == 0) {
     double sum = 0.0;
     for (int q = 0; q < NT / 64; ++q) sum += red[q];
-    A.xpart[blockIdx.y * gridDim.x + blockIdx.x] = sum;
+    const int b = blockIdx.y * gridDim.x + blockIdx.x;
+    if (A.xacc && A.post == 2) A.xacc[b] += 0.5 * A.dt * A.xp1[b] + A.dt * sum;
+    else A.xpart[b] = sum;
   }
 
   // ---- gather: one value (cell, v) per item: U_bar from the cell's face
@@ -450,8 +469,13 @@ hipError_t launch_vjp_tile2(const AdjArgs& A, int form, hipStream_t s) {
   AdjArgs a = A;
   void* args[] = {(void*)&a};
   hipError_t e = hipLaunchKernel(tile2_kernel_ptr<kTX, kTY, kTileThreads>(form), grid, block, args, 0, s);
-  if (e != hipSuccess || A.post != 2) return e;
+  if (e != hipSuccess || A.post != 2 || A.xacc) return e;
   hipLaunchKernelGGL(adj_xi_fold_kernel, dim3(1), dim3(kAdjThreads), 0, s, A.xp1, A.xp2, A.nblock, A.dt, A.dJdxi);
+  return hipGetLastError();
+}
+
+hipError_t launch_xi_acc_fold(double* acc, int m, double* dJdxi, hipStream_t s) {
+  hipLaunchKernelGGL(adj_acc_fold_kernel, dim3(1), dim3(kAdjThreads), 0, s, acc, m, dJdxi);
   return hipGetLastError();
 }
 

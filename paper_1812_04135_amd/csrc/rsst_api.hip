@@ -246,8 +246,11 @@ int rsst_init(const rsst_config* cfg, void* stream, rsst_handle* out) {
     }
   }
   // zeroed before any launch on any stream
+  const size_t adj_z = h->adj_work ? rsstk::adjoint_zeroed_offset(cfg->ndim, cfg->n, h->ncell) : 0;
+  const size_t adj_n = h->adj_work ? rsstk::adjoint_workspace_doubles(cfg->ndim, cfg->n, h->ncell) : 0;
   if (hipMemsetAsync(h->scal, 0, nscal * sizeof(double), s) != hipSuccess ||
       hipMemsetAsync(h->blkmax, 0, (size_t)a.nblk * sizeof(double), s) != hipSuccess ||
+      (adj_n > adj_z && hipMemsetAsync(h->adj_work + adj_z, 0, (adj_n - adj_z) * sizeof(double), s) != hipSuccess) ||
       hipStreamSynchronize(s) != hipSuccess) {
     rsst_destroy(h);
     return RSST_E_DEVICE;
@@ -412,8 +415,7 @@ int rsst_destroy(rsst_handle h) {
   return RSST_OK;
 }
 
-static int adjoint_pullback(rsst_handle h, const void* U, const void* U1, double* lam, double dt, double* dJdxi,
-                            hipStream_t s) {
+static rsstk::AdjointPlan adjoint_plan(rsst_handle h) {
   const rsst_config& c = h->cfg;
   rsstk::AdjointPlan p{};
   p.ndim = c.ndim;
@@ -429,28 +431,57 @@ static int adjoint_pullback(rsst_handle h, const void* U, const void* U1, double
   p.form = c.form;
   p.ncell = h->ncell;
   p.work = h->adj_work;
-  return check(rsstk::launch_adjoint_step(p, (const double*)U, (const double*)U1, lam, dt, dJdxi, s));
+  return p;
+}
+
+// U1 = U + dt R(U) into the stage buffer: the same stage-1 kernel as the
+// forward step.
+static hipError_t recompute_u1(rsst_handle h, const void* U, double dt, hipStream_t s) {
+  StageArgs a = h->args;
+  a.dt_fixed = dt;
+  a.uin = U;
+  a.un = nullptr;
+  a.uout = h->u1;
+  return rsstk::launch_stage(a, 1, s);
 }
 
 int rsst_adjoint_step(rsst_handle h, const void* U, double* lam, double dt, double* dJdxi, void* stream) {
   if (!h || !U || !lam || !dJdxi || !(dt > 0.0) || !std::isfinite(dt)) return RSST_E_ARG;
   if (!h->adj_work) return RSST_E_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
-  // U1 = U + dt R(U), the same stage-1 kernel as the forward step
-  StageArgs a = h->args;
-  a.dt_fixed = dt;
-  a.uin = U;
-  a.un = nullptr;
-  a.uout = h->u1;
-  if (rsstk::launch_stage(a, 1, s) != hipSuccess) return RSST_E_DEVICE;
-  return adjoint_pullback(h, U, h->u1, lam, dt, dJdxi, s);
+  if (recompute_u1(h, U, dt, s) != hipSuccess) return RSST_E_DEVICE;
+  return check(rsstk::launch_adjoint_step(adjoint_plan(h), (const double*)U, (const double*)h->u1, lam, dt, dJdxi,
+                                          false, s));
 }
 
 int rsst_adjoint_step_u1(rsst_handle h, const void* U, const void* U1, double* lam, double dt, double* dJdxi,
                          void* stream) {
   if (!h || !U || !U1 || !lam || !dJdxi || !(dt > 0.0) || !std::isfinite(dt)) return RSST_E_ARG;
   if (!h->adj_work) return RSST_E_UNSUPPORTED;
-  return adjoint_pullback(h, U, U1, lam, dt, dJdxi, (hipStream_t)stream);
+  return check(rsstk::launch_adjoint_step(adjoint_plan(h), (const double*)U, (const double*)U1, lam, dt, dJdxi,
+                                          false, (hipStream_t)stream));
+}
+
+int rsst_adjoint_run(rsst_handle h, const void* const* U_list, const void* const* U1_list, int nsteps, double* lam,
+                     double dt, double* dJdxi, void* stream) {
+  if (!h || !U_list || !lam || !dJdxi || nsteps < 0 || !(dt > 0.0) || !std::isfinite(dt)) return RSST_E_ARG;
+  if (!h->adj_work) return RSST_E_UNSUPPORTED;
+  for (int n = 0; n < nsteps; ++n)
+    if (!U_list[n] || (U1_list && !U1_list[n])) return RSST_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  const rsstk::AdjointPlan p = adjoint_plan(h);
+  // 2D: each step adds its dJ/dxi share per tile into the run accumulator,
+  // folded into dJdxi once after the last step
+  const bool defer = p.ndim == 2;
+  for (int n = nsteps - 1; n >= 0; --n) {
+    const void* U1 = U1_list ? U1_list[n] : h->u1;
+    if (!U1_list && recompute_u1(h, U_list[n], dt, s) != hipSuccess) return RSST_E_DEVICE;
+    if (rsstk::launch_adjoint_step(p, (const double*)U_list[n], (const double*)U1, lam, dt, dJdxi, defer, s) !=
+        hipSuccess)
+      return RSST_E_DEVICE;
+  }
+  if (defer && nsteps > 0 && rsstk::launch_adjoint_xi_fold(p, dJdxi, s) != hipSuccess) return RSST_E_DEVICE;
+  return check(hipGetLastError());
 }
 
 int rsst_step_noalloc(const rsst_config* cfg, void* U, double dt_fixed, uint32_t* flags, void* stream) {

@@ -139,22 +139,26 @@ def _cons_torch(rho, vx, vy, P, gamma=5.0 / 3.0):
 
 
 def test_rollout_checkpointing_and_oracle_directional_derivatives():
-    """Checkpoints every 20 steps give the same bits as no checkpoints, and
-    the gradient of the final kinetic energy matches the oracle's duals."""
+    """Checkpoints every 20 steps give the same bits as no checkpoints, the
+    kept trajectory the same dJ/dU0 bits and dJ/dxi to rounding, and the
+    gradient of the final kinetic energy matches the oracle's duals."""
     from paper_1812_04135_amd.rollout import kinetic_energy, rollout
     cfg, U0 = W.random_state(2, [24, 20], seed_k=730, xi=6.0, form="pvs",
                              bc_lo=["periodic", "reflect"], g=[0.0, -0.3], mach=0.1)
     nsteps = 45
     dt = 0.4 * oracle.cfl_dt(cfg, U0)
     grads = []
-    for K in (20, 1000):
+    for K in (20, 1000, 1):
         U = torch.from_numpy(U0).cuda().requires_grad_(True)
         xi = torch.tensor(cfg["xi"], dtype=torch.float64, requires_grad=True)
-        J = kinetic_energy(rollout(U, xi, cfg, nsteps, dt, checkpoint_every=K), cfg)
+        UN = rollout(U, xi, cfg, nsteps, dt, checkpoint_every=K)
+        J = kinetic_energy(UN, cfg)
         J.backward()
-        grads.append((U.grad.cpu().numpy(), float(xi.grad)))
+        grads.append((U.grad.cpu().numpy(), float(xi.grad), UN.detach().cpu().numpy()))
     assert np.array_equal(grads[0][0], grads[1][0]) and grads[0][1] == grads[1][1]
-    gU, gxi = grads[0]
+    assert np.array_equal(grads[0][2], grads[2][2]) and np.array_equal(grads[0][0], grads[2][0])
+    assert abs(grads[2][1] - grads[0][1]) <= 1e-13 * abs(grads[0][1])
+    gU, gxi = grads[0][:2]
     rng = np.random.default_rng(W.seed(73))
     d = rng.standard_normal((4, U0.size)) * 1e-2
     dx = np.array([0.0, 0.0, 1.0, -0.5])
@@ -326,3 +330,37 @@ def test_step_out_rejects_aliased_buffers():
         with pytest.raises(R.RsstError):
             s.step_out(U, U1, Un, 1e-3)
     s.close()
+
+
+def test_adjoint_run_matches_per_step_calls():
+    """One rsst_adjoint_run over a kept trajectory gives the bits of lam of
+    the per-step calls and dJ/dxi to rounding; with U1_list = None (stage
+    values recomputed) the same; an empty run changes nothing."""
+    for ndim, n, bc, g in ((2, [37, 30], ["reflect", "periodic"], [0.2, -0.1]),
+                           (1, [40], ["reflect"], [-0.3]),
+                           (3, [12, 10, 8], ["periodic", "periodic", "reflect"], [0.0, 0.0, -0.5])):
+        cfg, U0 = W.random_state(ndim, n, seed_k=760 + sum(n), xi=4.0, form="pms", bc_lo=bc, g=g)
+        dt = 0.5 * oracle.cfl_dt(cfg, U0)
+        s = R.Solver(cfg, adjoint=True)
+        N = 6
+        traj = [torch.from_numpy(np.ascontiguousarray(U0)).cuda()]
+        st1 = []
+        for _ in range(N):
+            st1.append(torch.empty_like(traj[0]))
+            traj.append(torch.empty_like(traj[0]))
+            s.step_out(traj[-2], st1[-1], traj[-1], dt)
+        lam0 = torch.from_numpy(np.random.default_rng(W.seed(76)).standard_normal(U0.shape)).cuda()
+        ref, dref = lam0.clone(), torch.zeros(1, dtype=torch.float64, device="cuda")
+        for k in reversed(range(N)):
+            s.adjoint_step(traj[k], ref, dt, dref, U1=st1[k])
+        for U1_list in (st1, None):
+            lam, d = lam0.clone(), torch.zeros(1, dtype=torch.float64, device="cuda")
+            s.adjoint_run(traj[:N], U1_list, lam, dt, d)
+            torch.cuda.synchronize()
+            assert torch.equal(lam, ref), (ndim, U1_list is None)
+            assert abs(float(d) - float(dref)) <= 1e-13 * abs(float(dref)), (ndim, float(d), float(dref))
+        lam, d = lam0.clone(), torch.zeros(1, dtype=torch.float64, device="cuda")
+        s.adjoint_run([], [], lam, dt, d)
+        torch.cuda.synchronize()
+        assert torch.equal(lam, lam0) and float(d) == 0.0
+        s.close()
