@@ -169,9 +169,9 @@ struct Tile2 {
   // the states of the faces of the reverse phase, formed in the flux phase:
   // L.u, R.u, L.c, R.c, [q][oy][k] and [q][k][ox] like the cotangents
   static constexpr int NF = 10 * (TY * LXN + LYN * TX);
-  // U, W, Delta_bar, fluxes then face cotangents, face states, direct U_bar
-  // and lam of the tile's cells
-  static constexpr int NLDS = NU + 2 * ND + (NG > NL ? NG : NL) + NF + 2 * 4 * NC;
+  // U, Delta_bar, fluxes then face cotangents, face states, direct U_bar of
+  // the tile's cells
+  static constexpr int NLDS = NU + ND + (NG > NL ? NG : NL) + NF + 4 * NC;
 };
 
 template <int FORM, int TX, int TY, int NT>
@@ -181,8 +181,7 @@ __global__ void __launch_bounds__(NT) adj_tile2_kernel(AdjArgs A) {
   constexpr int GXN = T::GXN, GYN = T::GYN, LXN = T::LXN, LYN = T::LYN, NC = T::NC;
   __shared__ double lds[T::NLDS];
   double* const Us = lds;
-  double* const Ws = Us + T::NU;
-  double* const Ds = Ws + T::ND;
+  double* const Ds = Us + T::NU;
   double* const Gx = Ds + T::ND;
   double* const Gy = Gx + 4 * DY * GXN;
   double* const Lx = Ds + T::ND;  // after the cell phase, over the fluxes
@@ -192,11 +191,15 @@ __global__ void __launch_bounds__(NT) adj_tile2_kernel(AdjArgs A) {
   double* const FX = Ds + T::ND + (T::NG > T::NL ? T::NG : T::NL);  // face states, x
   double* const FY = FX + 10 * TY * LXN;                             // face states, y
   double* const Bs = FY + 10 * LYN * TX;                             // direct U_bar, [v][cell]
-  double* const Ls = Bs + 4 * NC;                                    // lam (second VJP), [v][cell]
   __shared__ double red[NT / 64];
 
   const int tid = threadIdx.x;
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+  // tile of this workgroup: dispatch goes round-robin over the 8 XCDs, so
+  // consecutive workgroups take tiles nblock/8 apart and each XCD a
+  // contiguous run of tile rows, whose shared halos meet in its own L2
+  const int gxt = (A.n[0] + TX - 1) / TX;
+  const int tile = ((A.nblock & 7) == 0) ? (blockIdx.x & 7) * (A.nblock >> 3) + (blockIdx.x >> 3) : blockIdx.x;
+  const int x0 = (tile % gxt) * TX, y0 = (tile / gxt) * TY;
   const int nx = A.n[0], ny = A.n[1];
   const int rxl = A.refl_lo[0], rxh = A.refl_hi[0], ryl = A.refl_lo[1], ryh = A.refl_hi[1];
   const Consts K = adj_consts<2>(A);
@@ -211,9 +214,34 @@ __global__ void __launch_bounds__(NT) adj_tile2_kernel(AdjArgs A) {
     return (long long)cy * nx + cx;
   };
 
-  // ---- load U over its window, W over the cell phase's window and, for
-  // the second VJP, lam of the tile's cells (all loads in flight together)
-  for (int t = tid; t < UX * UY + DX * DY + (A.post == 2 ? NC : 0); t += NT) {
+  // ---- load U over its window into LDS; W of this thread's cell-phase
+  // item and, for its gather value (cell, v), W and the second VJP's lam
+  // wait in registers (all loads in flight together, only U's awaited here)
+  static_assert(NT == 4 * NC, "one gather value (cell, v) per thread");
+  static_assert(NT >= NC + 4 * (TX + TY), "one cell-phase item per thread");
+  const int ge = tid % NC, gv = tid / NC;
+  const int gx = x0 + ge % TX, gy = y0 + ge / TX;
+  const bool gin = gx < nx && gy < ny;
+  const long long gq = gv * A.ncell + (long long)gy * nx + gx;
+  // the cell-phase item of this thread: the tile's own cells first, then
+  // the two rows and columns around it (corners excluded)
+  int crx = 0, cry = 0;
+  const bool citem = tid < NC + 4 * (TX + TY);
+  if (tid < NC) {
+    crx = tid % TX + 2;
+    cry = tid / TX + 2;
+  } else if (tid < NC + 4 * TX) {
+    const int h = tid - NC, band = h / TX;
+    crx = h % TX + 2;
+    cry = band < 2 ? band : TY + band;
+  } else if (citem) {
+    const int h = tid - NC - 4 * TX, band = h / TY;
+    cry = h % TY + 2;
+    crx = band < 2 ? band : TX + band;
+  }
+  const int cxp = x0 - 2 + crx, cyp = y0 - 2 + cry;
+  const bool creal = citem && real_pos(cxp, nx, rxl, rxh) && real_pos(cyp, ny, ryl, ryh);
+  for (int t = tid; t < UX * UY; t += NT) {
     if (t < UX * UY) {
       const int px = t % UX, py = t / UX;
       bool negx, negy;
@@ -224,21 +252,17 @@ __global__ void __launch_bounds__(NT) adj_tile2_kernel(AdjArgs A) {
         if ((v == 1 && negx) || (v == 2 && negy)) val = -val;
         Us[(v * UY + py) * UX + px] = val;
       }
-    } else if (t < UX * UY + DX * DY) {
-      const int s = t - UX * UY, rx = s % DX, ry = s / DX;
-      bool negx, negy;
-      const long long c = cell_at(x0 - 2 + rx, y0 - 2 + ry, negx, negy);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Ws[(v * DY + ry) * DX + rx] = A.W[v * A.ncell + c];
-    } else {
-      const int s = t - UX * UY - DX * DY;
-      const int x = x0 + s % TX, y = y0 + s / TX;
-      if (x < nx && y < ny) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) Ls[v * NC + s] = A.lam[v * A.ncell + (long long)y * nx + x];
-      }
     }
   }
+  double Rb[4] = {0.0, 0.0, 0.0, 0.0};
+  if (creal) {
+    bool negx, negy;
+    const long long c = cell_at(cxp, cyp, negx, negy);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Rb[v] = A.W[v * A.ncell + c];
+  }
+  const double w_own = gin ? A.W[gq] : 0.0;
+  const double lam_own = (A.post == 2 && gin) ? A.lam[gq] : 0.0;
   __syncthreads();
 
   // ---- forward fluxes
@@ -278,24 +302,12 @@ __global__ void __launch_bounds__(NT) adj_tile2_kernel(AdjArgs A) {
   // tile's own cells keep their direct U_bar and the f part of xi_bar
   double xib = 0.0;
   const double hdx = 0.5 * A.inv_dx[0], hdy = 0.5 * A.inv_dx[1];
-  for (int t = tid; t < NC + 4 * (TX + TY); t += NT) {
-    int rx, ry;
-    if (t < NC) {
-      rx = t % TX + 2;
-      ry = t / TX + 2;
-    } else if (t < NC + 4 * TX) {
-      const int h = t - NC, band = h / TX;
-      rx = h % TX + 2;
-      ry = band < 2 ? band : TY + band;
-    } else {
-      const int h = t - NC - 4 * TX, band = h / TY;
-      ry = h % TY + 2;
-      rx = band < 2 ? band : TX + band;
-    }
-    const int x = x0 - 2 + rx, y = y0 - 2 + ry;
+  if (citem) {
+    const int t = tid, rx = crx, ry = cry;
+    const int x = cxp, y = cyp;
     double Db[4] = {0.0, 0.0, 0.0, 0.0};
-    if (real_pos(x, nx, rxl, rxh) && real_pos(y, ny, ryl, ryh)) {
-      double Dl[4] = {0.0, 0.0, 0.0, 0.0}, u[4], Rb[4], ub[4] = {0.0, 0.0, 0.0, 0.0};
+    if (creal) {
+      double Dl[4] = {0.0, 0.0, 0.0, 0.0}, u[4], ub[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const double gl = Gx[(v * DY + ry) * GXN + rx], gh = Gx[(v * DY + ry) * GXN + rx + 1];
@@ -307,8 +319,6 @@ __global__ void __launch_bounds__(NT) adj_tile2_kernel(AdjArgs A) {
         Dl[v] -= (gh - gl) * hdy;
       }
       Uc(rx + 2, ry + 2, u);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Rb[v] = Ws[(v * DY + ry) * DX + rx];
       const double fb = rate_vjp<2, FORM>(u, Dl, Rb, A, Db, ub);
       if (t < NC) {
 #pragma unroll
@@ -375,19 +385,18 @@ __global__ void __launch_bounds__(NT) adj_tile2_kernel(AdjArgs A) {
   if (tid == 0) {
     double sum = 0.0;
     for (int q = 0; q < NT / 64; ++q) sum += red[q];
-    const int b = blockIdx.y * gridDim.x + blockIdx.x;
+    const int b = tile;
     if (A.xacc && A.post == 2) A.xacc[b] += 0.5 * A.dt * A.xp1[b] + A.dt * sum;
     else A.xpart[b] = sum;
   }
 
-  // ---- gather: one value (cell, v) per item: U_bar from the cell's face
+  // ---- gather: one value (cell, v) per thread: U_bar from the cell's face
   // cotangents, the reverse of its MC half slopes and those of its
   // neighbours on both axes; then mu or the new lam
-  for (int t = tid; t < 4 * NC; t += NT) {
-    const int e = t % NC, v = t / NC;
+  if (gin) {
+    const int e = ge, v = gv;
     const int ox = e % TX, oy = e / TX;
-    const int x = x0 + ox, y = y0 + oy;
-    if (x >= nx || y >= ny) continue;
+    const int x = gx, y = gy;
     const int px = ox + 4, py = oy + 4;
     double ub = Bs[v * NC + e];
     const double* const lx = Lx + (v * TY + oy) * LXN;
@@ -439,11 +448,10 @@ __global__ void __launch_bounds__(NT) adj_tile2_kernel(AdjArgs A) {
       cot(ucol[(py - 2) * UX], ucol[(py - 1) * UX], ucol[py * UX], ly[(oy + 1) * TX], ryr[oy * TX], lb, rb);
       ub += rb;
     }
-    const long long q = v * A.ncell + (long long)y * nx + x;
-    const double w = Ws[(v * DY + oy + 2) * DX + ox + 2];  // W of this cell
-    if (A.post == 1) A.mu[q] = 0.5 * (w + A.dt * ub);       // W = lam
-    else if (A.post == 2) A.lam[q] = 0.5 * Ls[v * NC + e] + w + A.dt * ub;  // W = mu
-    else A.out[q] = ub;
+    const double w = w_own;  // W of this value
+    if (A.post == 1) A.mu[gq] = 0.5 * (w + A.dt * ub);       // W = lam
+    else if (A.post == 2) A.lam[gq] = 0.5 * lam_own + w + A.dt * ub;  // W = mu
+    else A.out[gq] = ub;
   }
 
 }
@@ -465,7 +473,7 @@ void* tile2_kernel_ptr(int form) {
 int tile2_nblock(const int n[3]) { return ((n[0] + kTX - 1) / kTX) * ((n[1] + kTY - 1) / kTY); }
 
 hipError_t launch_vjp_tile2(const AdjArgs& A, int form, hipStream_t s) {
-  const dim3 grid((A.n[0] + kTX - 1) / kTX, (A.n[1] + kTY - 1) / kTY), block(kTileThreads);
+  const dim3 grid(tile2_nblock(A.n)), block(kTileThreads);
   AdjArgs a = A;
   void* args[] = {(void*)&a};
   hipError_t e = hipLaunchKernel(tile2_kernel_ptr<kTX, kTY, kTileThreads>(form), grid, block, args, 0, s);
