@@ -174,6 +174,16 @@ int rsst_stage(rsst_handle h, void* U, int stage, double dt_fixed, void* stream)
  * to hand U1 to rsst_adjoint_step_u1. */
 int rsst_step_out(rsst_handle h, const void* U, void* U1, void* Unext, double dt_fixed, void* stream);
 
+/* nsteps calls of rsst_step_out in one call, keeping the trajectory:
+ * U_list[n+1] = the step from U_list[n], U1_list[n] its stage value, for
+ * n = 0 .. nsteps-1 (U_list: host array of nsteps + 1 device pointers,
+ * U_list[0] the start state, read only; U1_list: nsteps).  Same results as
+ * the separate calls; every launch on `stream` from this call.  RSST_E_ARG
+ * for a NULL entry or nsteps < 0; a pair of equal pointers within one step
+ * is refused as rsst_step_out refuses it, after the steps before it ran. */
+int rsst_steps_out(rsst_handle h, void* const* U_list, void* const* U1_list, int nsteps, double dt_fixed,
+                   void* stream);
+
 /* nsteps calls of rsst_step, with the same results.  A 1D grid runs as one
  * workgroup, so for ndim = 1 all nsteps steps are one launch (both stages,
  * the CFL maximum and the next dt of every step inside it, U written once at

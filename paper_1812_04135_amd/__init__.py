@@ -90,6 +90,7 @@ def lib():
         L.rsst_adjoint_step.argtypes = [vp, vp, vp, ctypes.c_double, vp, vp]
         L.rsst_adjoint_step_u1.argtypes = [vp, vp, vp, vp, ctypes.c_double, vp, vp]
         L.rsst_step_out.argtypes = [vp, vp, vp, vp, ctypes.c_double, vp]
+        L.rsst_steps_out.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int, ctypes.c_double, vp]
         L.rsst_adjoint_run.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int, vp,
                                        ctypes.c_double, vp, vp]
         L.rsst_batch_plan.argtypes = [ctypes.POINTER(rsst_config), ctypes.c_int, ctypes.POINTER(ctypes.c_int),
@@ -98,7 +99,7 @@ def lib():
                      "rsst_diag", "rsst_poll", "rsst_destroy", "rsst_batch_init", "rsst_batch_set_tiles",
                      "rsst_batch_get_tiles", "rsst_batch_run", "rsst_batch_times", "rsst_batch_poll",
                      "rsst_batch_destroy", "rsst_batch_plan", "rsst_adjoint_step", "rsst_adjoint_step_u1",
-                     "rsst_step_out", "rsst_adjoint_run"):
+                     "rsst_step_out", "rsst_adjoint_run", "rsst_steps_out"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -185,6 +186,17 @@ def rsst_step(h, U, dt_fixed: float = 0.0, stream=None):
 def rsst_step_out(h, U, U1, Unext, dt_fixed: float = 0.0, stream=None):
     _check(lib().rsst_step_out(h, _ptr(U), _ptr(U1), _ptr(Unext), float(dt_fixed), _stream(stream)),
            "rsst_step_out")
+
+
+def rsst_steps_out(h, U_list, U1_list, dt_fixed: float = 0.0, stream=None):
+    """len(U1_list) out-of-place steps: U_list[n+1] from U_list[n], keeping
+    U1_list[n] (U_list has one entry more)."""
+    n = len(U1_list)
+    if len(U_list) != n + 1:
+        raise ValueError("rsst_steps_out: U_list needs len(U1_list) + 1 entries")
+    us = (ctypes.c_void_p * (n + 1))(*[_ptr(u) for u in U_list])
+    u1s = (ctypes.c_void_p * max(n, 1))(*[_ptr(u) for u in U1_list])
+    _check(lib().rsst_steps_out(h, us, u1s, n, float(dt_fixed), _stream(stream)), "rsst_steps_out")
 
 
 def rsst_step_noalloc(cfg: rsst_config, U, dt_fixed: float = 0.0, flags=None, stream=None):
@@ -297,6 +309,10 @@ class Solver:
         """One step out of place: U1 = U + dt R(U), Unext = the stepped state
         (U unchanged; same bits as step)."""
         rsst_step_out(self.h, U, U1, Unext, dt_fixed, stream)
+
+    def steps_out(self, U_list, U1_list, dt_fixed=0.0, stream=None):
+        """Steps out of place along a kept trajectory (see rsst_steps_out)."""
+        rsst_steps_out(self.h, U_list, U1_list, dt_fixed, stream)
 
     def adjoint_run(self, U_list, U1_list, lam, dt, dJdxi, stream=None):
         """The adjoint of the steps U_list[n] -> U_list[n+1] (stage values

@@ -325,6 +325,18 @@ int rsst_step_out(rsst_handle h, const void* U, void* U1, void* Unext, double dt
   return RSST_OK;
 }
 
+int rsst_steps_out(rsst_handle h, void* const* U_list, void* const* U1_list, int nsteps, double dt_fixed,
+                   void* stream) {
+  if (!h || !U_list || !U1_list || nsteps < 0 || !std::isfinite(dt_fixed)) return RSST_E_ARG;
+  for (int n = 0; n < nsteps; ++n)
+    if (!U_list[n] || !U1_list[n] || !U_list[n + 1]) return RSST_E_ARG;
+  for (int n = 0; n < nsteps; ++n) {
+    const int st = rsst_step_out(h, U_list[n], U1_list[n], U_list[n + 1], dt_fixed, stream);
+    if (st != RSST_OK) return st;
+  }
+  return RSST_OK;
+}
+
 int rsst_steps(rsst_handle h, void* U, int nsteps, double dt_fixed, void* stream) {
   if (nsteps < 0) return RSST_E_ARG;
   if (h && U && std::isfinite(dt_fixed) && nsteps > 0 && h->cfg.ndim == 1) {

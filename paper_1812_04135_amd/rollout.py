@@ -8,7 +8,7 @@ hand-written adjoint, giving dJ/dU0 and dJ/dxi.
 Two ways to keep what the backward needs:
   * the whole trajectory (checkpoint_every = 1, or "auto" where the states
     and stage values of every step fit in half of the free device memory):
-    the forward steps out of place (rsst_step_out) into preallocated
+    the forward steps out of place (rsst_steps_out, one call) into preallocated
     buffers, keeping each state U_n and stage value U1_n, and the backward
     is one rsst_adjoint_run call over them, no step recomputed;
   * checkpoints (checkpoint_every = K > 1): the forward keeps the state at
@@ -53,8 +53,7 @@ class RSSTRollout(torch.autograd.Function):
             out = U0.detach().contiguous().clone()
             if nsteps > 0:
                 traj[0].copy_(out)
-                for n in range(nsteps):
-                    solver.step_out(traj[n], stage1[n], traj[n + 1] if n + 1 < nsteps else out, dt)
+                solver.steps_out([traj[n] for n in range(nsteps)] + [out], [stage1[n] for n in range(nsteps)], dt)
             ctx.traj, ctx.stage1, ctx.ckpts = traj, stage1, None
             return out
         U = U0.detach().contiguous().clone()

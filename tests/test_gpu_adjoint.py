@@ -364,3 +364,29 @@ def test_adjoint_run_matches_per_step_calls():
         torch.cuda.synchronize()
         assert torch.equal(lam, lam0) and float(d) == 0.0
         s.close()
+
+
+def test_steps_out_matches_single_steps():
+    """rsst_steps_out leaves the trajectory and stage values of the separate
+    rsst_step_out calls, bit for bit, and refuses a missing entry."""
+    cfg, U0 = W.random_state(2, [33, 27], seed_k=770, xi=5.0, form="pvs", bc_lo=["periodic", "reflect"],
+                             g=[0.0, -0.4])
+    dt = 0.5 * oracle.cfl_dt(cfg, U0)
+    a, b = R.Solver(cfg), R.Solver(cfg)
+    N = 5
+    u0 = torch.from_numpy(np.ascontiguousarray(U0)).cuda()
+    ta = [u0.clone()] + [torch.empty_like(u0) for _ in range(N)]
+    sa = [torch.empty_like(u0) for _ in range(N)]
+    tb = [u0.clone()] + [torch.empty_like(u0) for _ in range(N)]
+    sb = [torch.empty_like(u0) for _ in range(N)]
+    for n in range(N):
+        a.step_out(ta[n], sa[n], ta[n + 1], dt)
+    b.steps_out(tb, sb, dt)
+    torch.cuda.synchronize()
+    for n in range(N):
+        assert torch.equal(ta[n + 1], tb[n + 1]) and torch.equal(sa[n], sb[n]), n
+    assert a.time() == b.time()
+    with pytest.raises(ValueError):
+        b.steps_out(tb[:N], sb, dt)
+    a.close()
+    b.close()
