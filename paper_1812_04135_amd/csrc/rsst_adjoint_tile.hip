@@ -5,10 +5,12 @@
 // bits), but each workgroup owns a TX x TY tile of output cells and forms
 // everything it needs in LDS, so a VJP is one launch with no full-field
 // scratch in HBM:
-//   load    U over the tile and four cells around it (boundary rules
-//           applied: periodic wrap, or the mirror image with the normal
-//           momentum negated);
-//   fluxes  G = 2 Fhat at every face of the cells within two of the tile;
+//   load    U over the tile and four cells around it into LDS (boundary
+//           rules applied: periodic wrap, or the mirror image with the
+//           normal momentum negated); each thread's own W (and, second VJP,
+//           lam) into registers;
+//   fluxes  G = 2 Fhat at every face of the cells within two of the tile,
+//           keeping the states of the faces the reverse needs;
 //   cells   for those cells, the increments Delta, then the reverse of the
 //           correction and gravity: Delta_bar (zero outside a wall), and for
 //           the tile's own cells the direct part of U_bar and the f part of
@@ -21,11 +23,14 @@
 //   gather  U_bar of each tile cell: its face-state cotangents, the reverse
 //           of its MC half slopes and those of its neighbours on both axes;
 //           then mu (first VJP) or the new lam (second VJP).
-// A face shared by two tiles is formed by both (the same bits); the partial
-// sums of xi_bar count each cell and each face once, in the tile that owns
-// it (a face i+1/2 belongs to cell i, a low wall face to cell 0).  The last
-// workgroup of the second VJP folds both VJPs' partial sums into dJ/dxi in
-// a fixed order.
+// 16 x 16 tiles, 1024 threads (four waves per SIMD), 124 KiB of LDS: one
+// workgroup per CU.  A face shared by two tiles is formed by both (the same
+// bits); the partial sums of xi_bar count each cell and each face once, in
+// the tile that owns it (a face i+1/2 belongs to cell i, a low wall face to
+// cell 0).  After the second VJP a one-workgroup launch folds both VJPs'
+// partial sums into dJ/dxi in a fixed order, or, over a run of steps, the
+// second VJP adds its tile's share into a per-tile accumulator folded once
+// at the end (no atomics, no cross-workgroup waits).
 #include <hip/hip_runtime.h>
 
 #include "rsst_adjoint.h"
