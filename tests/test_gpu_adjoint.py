@@ -42,6 +42,9 @@ CASES = [
     (2, [41, 35], "pvs", ["reflect", "periodic"], [0.2, 0.0], 5.0),
     (2, [40, 50], "pd", ["periodic", "reflect"], [0.0, -0.4], 3.0),
     (2, [70, 33], "dms", ["reflect", "reflect"], [0.1, -0.3], 7.0),
+    # tile counts that are multiples of 8: the XCD-ordered tile mapping
+    (2, [64, 32], "pms", ["reflect", "reflect"], [0.2, -0.3], 4.0),
+    (2, [128, 64], "pvs", ["periodic", "reflect"], [0.0, -0.5], 6.0),
     (3, [12, 10, 8], "pvs", ["periodic", "periodic", "reflect"], [0.0, 0.0, -0.5], 8.0),
     (3, [9, 8, 7], "pd", ["reflect", "reflect", "reflect"], [0.1, 0.0, -0.4], 3.0),
 ]
