@@ -125,9 +125,12 @@ typedef struct rsst_config {
 enum rsst_eos { RSST_EOS_IDEAL = 0, RSST_EOS_VDW = 1 };
 
 enum rsst_flag {
-  RSST_WITH_ADJOINT = 1  /* rsst_init also reserves the workspace of
-                            rsst_adjoint_step (FP64 only):
-                            nvar * ncell * (2 ndim + 3) doubles               */
+  RSST_WITH_ADJOINT = 1  /* rsst_init also reserves the workspace of the
+                            adjoint calls (FP64 only): on a 2D grid
+                            nvar * ncell doubles and three per 16 x 16 tile,
+                            else nvar * ncell * (2 ndim + 3) doubles and four
+                            per 256 cells.  The adjoint calls of one handle
+                            share it: order them on one stream.               */
 };
 
 typedef struct rsst_solver* rsst_handle;
