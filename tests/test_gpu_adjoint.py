@@ -230,10 +230,14 @@ def test_finite_differences_of_kinetic_energy_bubble():
 
 def test_adjoint_full_size_finite_differences():
     """The adjoint workload at full size: 256^2 bubble, xi = 10, 400 steps at
-    the frozen CFL dt, checkpoints every 20 steps; two smooth density
-    directions against central differences (h = 1e-6)."""
+    the frozen CFL dt, checkpoints every 20 steps; 16 smooth density
+    directions against central differences.  At h = 1e-6 every direction is
+    within 1e-4.  At h = 1e-7 the median is within 1e-6 and the max within
+    1e-4: the difference error here is linear in h (J is piecewise smooth,
+    the limiter and the LLF maximum switch branch where +-h d crosses a tie),
+    so the smaller step is the sharper check."""
     from paper_1812_04135_amd.rollout import kinetic_energy, rollout
-    cfg, U0, meta = W.adjoint2d(n=256, ndir=2)
+    cfg, U0, meta = W.adjoint2d(n=256, ndir=16)
     nsteps = 400
     dev = "cuda"
     vx, vy, P = (torch.from_numpy(meta[k]).to(dev) for k in ("vx", "vy", "P"))
@@ -251,13 +255,21 @@ def test_adjoint_full_size_finite_differences():
             s.steps(U, nsteps, dt)
             return float(kinetic_energy(U, cfg))
 
-    for q in range(2):
+    errs = {1e-6: [], 1e-7: []}
+    for q in range(16):
         d = torch.from_numpy(meta["dirs"][q]).to(dev)
-        fd = (J_at(rho0 + 1e-6 * d) - J_at(rho0 - 1e-6 * d)) / 2e-6
         ad = float((rho.grad * d).sum())
-        print(f"[fd full] dir {q}: fd {fd:.10e} adjoint {ad:.10e} rel {abs(fd - ad) / abs(ad):.2e}", flush=True)
-        assert abs(fd - ad) <= 1e-4 * abs(ad)
+        for h in errs:
+            fd = (J_at(rho0 + h * d) - J_at(rho0 - h * d)) / (2 * h)
+            errs[h].append(abs(fd - ad) / abs(ad))
+        print(f"[fd full] dir {q}: adjoint {ad:.10e} rel {errs[1e-6][-1]:.2e} (h 1e-6), "
+              f"{errs[1e-7][-1]:.2e} (h 1e-7)", flush=True)
     s.close()
+    e6, e7 = np.array(errs[1e-6]), np.array(errs[1e-7])
+    print(f"[fd full] median/max: h 1e-6 {np.median(e6):.2e}/{e6.max():.2e}, "
+          f"h 1e-7 {np.median(e7):.2e}/{e7.max():.2e}", flush=True)
+    assert e6.max() <= 1e-4
+    assert np.median(e7) <= 1e-6 and e7.max() <= 1e-4
 
 
 @pytest.mark.parametrize("K", [20, 15])
