@@ -71,6 +71,7 @@ __device__ __forceinline__ double stage_body3(const StageArgs& A, double* lds, i
   constexpr int SZ = (int)sizeof(ST);
   constexpr int NXP = 64 * NWXC, PX = NXP + 2;
   constexpr bool ONE = NWXC == 8;  // one thread-row: both tile edges
+  constexpr bool kEarlyOut = STAGE == 1 && !ONE && !HYD;
   const Geometry& G = A.geo;
   const int TS = G.ts, R = TS >> 1;
   const Carve3 C = carve3(TS, NWXC);
@@ -341,6 +342,23 @@ __device__ __forceinline__ double stage_body3(const StageArgs& A, double* lds, i
         flux2<NDIM, 1>(fh, fm, Fy_lo);
       }
     }
+    // the outside rows of the next plane.  Stage 1 issues them as soon as
+    // this plane's are finished: the tile that owns those rows read them at
+    // the top of the iteration before, so more of them are still in L2 than
+    // at the end of this iteration.  Where more is live across P3 and P4
+    // (stage 2's step-start state, both outside sides of a one-thread-row
+    // tile, the hydrostatic walls' levers) the longer live range would
+    // spill, so those issue them last.
+    auto load_outside = [&]() {
+      const int kn = min(kraw + 1, G.nm - 1);
+      load_cell_raw<NDIM, ST>(uin, kn, oc1, o1);
+      load_cell_raw<NDIM, ST>(uin, kn, oc2, o2);
+      if constexpr (ONE) {
+        load_cell_raw<NDIM, ST>(uin, kn, chi1, o3);
+        load_cell_raw<NDIM, ST>(uin, kn, chi2, o4);
+      }
+    };
+    if constexpr (kEarlyOut) load_outside();
     __syncthreads();  // B2
     if constexpr (STAGE == 2) {
 #pragma unroll
@@ -462,15 +480,7 @@ __device__ __forceinline__ double stage_body3(const StageArgs& A, double* lds, i
 #pragma unroll
       for (int v = 0; v < NV; ++v) { q0[c][v] = q1[c][v]; q1[c][v] = q2[c][v]; }
     }
-    {  // the outside rows of the next plane
-      const int kn = min(kraw + 1, G.nm - 1);
-      load_cell_raw<NDIM, ST>(uin, kn, oc1, o1);
-      load_cell_raw<NDIM, ST>(uin, kn, oc2, o2);
-      if constexpr (ONE) {
-        load_cell_raw<NDIM, ST>(uin, kn, chi1, o3);
-        load_cell_raw<NDIM, ST>(uin, kn, chi2, o4);
-      }
-    }
+    if constexpr (!kEarlyOut) load_outside();
   }
   return cmax;
 }
