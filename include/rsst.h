@@ -195,10 +195,11 @@ int rsst_steps_out(rsst_handle h, void* const* U_list, void* const* U1_list, int
  * leave U unchanged) are skipped. */
 int rsst_steps(rsst_handle h, void* U, int nsteps, double dt_fixed, void* stream);
 
-/* Synchronises the stream, then returns the time t and the dt the next CFL
- * step will use (formed on the host from the recorded maxima by the same
- * operations as on the device, so the same value; 0 before any state has
- * been recorded). */
+/* Returns the time t and the dt the next CFL step will use (Sec. 4.1, the
+ * Courant condition).  The dt is formed on the device, on the stream, by the
+ * grid maximum and dt code of stage 1 over the recorded per-workgroup maxima,
+ * so it has the same bits; it is 0 before any state has been recorded.
+ * Launches one small kernel, then synchronises the stream. */
 int rsst_get_time(rsst_handle h, double* t, double* dt_next, void* stream);
 
 /* FP64 diagnostics of U, summed over cells in a fixed order (deterministic):

@@ -369,22 +369,15 @@ int rsst_steps(rsst_handle h, void* U, int nsteps, double dt_fixed, void* stream
 
 int rsst_get_time(rsst_handle h, double* t, double* dt_next, void* stream) {
   if (!h) return RSST_E_ARG;
-  double v[2];
-  std::vector<double> bm((size_t)h->args.nblk);
-  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return RSST_E_DEVICE;
-  if (hipMemcpy(v, h->scal, 2 * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess ||
-      hipMemcpy(bm.data(), h->blkmax, bm.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+  hipStream_t s = (hipStream_t)stream;
+  // the dt the next stage 1 will form, by the same device code (0 before any
+  // state has been seen)
+  if (rsstk::launch_next_dt(h->args, s) != hipSuccess) return RSST_E_DEVICE;
+  double v[rsstk::kNumScalars];
+  if (hipStreamSynchronize(s) != hipSuccess ||
+      hipMemcpy(v, h->scal, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess)
     return RSST_E_DEVICE;
-  // the dt the next stage 1 would form (same operations, so the same bits):
-  // cfl h / max c_tot, cut at t_end; 0 before any state has been seen
-  double m = 0.0;
-  for (double x : bm) m = std::fmax(m, x);
-  double dn = 0.0;
-  if (m > 0.0) {
-    dn = h->args.cfl_h / m;
-    if (h->args.t_end > 0.0) dn = std::fmin(dn, std::fmax(h->args.t_end - v[rsstk::kTime], 0.0));
-  }
-  if (dt_next) *dt_next = dn;
+  if (dt_next) *dt_next = v[rsstk::kDtNext];
   if (t) *t = v[rsstk::kTime];
   return RSST_OK;
 }

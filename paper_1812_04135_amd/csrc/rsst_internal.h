@@ -8,8 +8,10 @@
 namespace rsstk {
 
 // Device-side scalars of one solver, in one small allocation.  kDtCur: the
-// dt of the step in progress (formed by stage 1, read by stage 2); kTime: t.
-enum Scalar { kDtCur = 0, kTime = 1, kMaxBits = 2, kDone = 3, kFlags = 4, kNumScalars = 8 };
+// dt of the step in progress (formed by stage 1, read by stage 2); kTime: t;
+// kDtNext: the dt the next stage 1 will form (written on request, for
+// reporting).
+enum Scalar { kDtCur = 0, kTime = 1, kMaxBits = 2, kDone = 3, kFlags = 4, kDtNext = 5, kNumScalars = 8 };
 
 // Launch geometry of the fused stage kernel.
 //   x (axis 0): one lane per cell, a row of nx cells spread over nwx waves;
@@ -68,6 +70,9 @@ hipError_t launch_stage_n(const StageArgs& a, int stage, hipStream_t s);
 template <typename ST>
 hipError_t launch_steps1d(const StageArgs& a1, const StageArgs& a2, int nsteps, hipStream_t s);
 hipError_t launch_prime(const StageArgs& a, const void* u, double t0, int set_t, hipStream_t s);
+// Writes scal[kDtNext]: the dt the next CFL stage 1 will form from the stored
+// per-workgroup maxima (same code, so the same bits), 0 if none is positive.
+hipError_t launch_next_dt(const StageArgs& a, hipStream_t s);
 hipError_t launch_diag(const StageArgs& a, const void* u, double* partial, int npartial,
                        double* out8, hipStream_t s);
 int diag_partials(long long ncell);

@@ -272,6 +272,19 @@ hipError_t launch_prime(const StageArgs& a, const void* u, double t0, int set_t,
                 : launch_prime_p<double>(a, u, t0, set_t, s);
 }
 
+// The next CFL step's dt, for reporting: one workgroup runs the grid maximum
+// and the dt formula of stage 1 over the stored maxima.
+__global__ void __launch_bounds__(256) next_dt_kernel(const StageArgs A) {
+  __shared__ double red[4];
+  const double m = grid_max_from_blocks(A, red);
+  if (threadIdx.x == 0) A.scal[kDtNext] = m > 0.0 ? cfl_dt_of_max(A, m) : 0.0;
+}
+
+hipError_t launch_next_dt(const StageArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(next_dt_kernel, dim3(1), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 int diag_partials(long long ncell) {
   long long nb = (ncell + kDiagThreads - 1) / kDiagThreads;
   return (int)(nb < kDiagBlocks ? nb : kDiagBlocks);

@@ -237,7 +237,7 @@ __device__ __forceinline__ int xcd_tile(int b, int nblk) {
 // every workgroup of stage 1 at its start, the same bits in each (a maximum
 // does not depend on its order).  Includes a workgroup barrier; red is not
 // written again in stage 1.
-__device__ __forceinline__ double cfl_dt_from_blocks(const StageArgs& A, double* red) {
+__device__ __forceinline__ double grid_max_from_blocks(const StageArgs& A, double* red) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   double m = 0.0;
   for (int b = threadIdx.x; b < A.nblk; b += blockDim.x) m = fmax(m, A.blkmax[b]);
@@ -246,10 +246,18 @@ __device__ __forceinline__ double cfl_dt_from_blocks(const StageArgs& A, double*
   __syncthreads();
   m = 0.0;
   for (int q = 0; q < (int)(blockDim.x >> 6); ++q) m = fmax(m, red[q]);
+  return m;
+}
+
+__device__ __forceinline__ double cfl_dt_of_max(const StageArgs& A, double m) {
   const double t = A.scal[kTime];
   double dt = A.cfl_h / m;
   if (A.t_end > 0.0) dt = fmin(dt, fmax(A.t_end - t, 0.0));
   return dt;
+}
+
+__device__ __forceinline__ double cfl_dt_from_blocks(const StageArgs& A, double* red) {
+  return cfl_dt_of_max(A, grid_max_from_blocks(A, red));
 }
 
 // Stage 2: the workgroup's largest c_tot of the new state, stored in its own
