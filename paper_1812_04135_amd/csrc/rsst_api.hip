@@ -203,7 +203,7 @@ const char* rsst_strerror(int s) {
   }
 }
 
-const char* rsst_version(void) { return "rsst-gfx950 stage-v19"; }
+const char* rsst_version(void) { return "rsst-gfx950 stage-v20"; }
 
 int rsst_init(const rsst_config* cfg, void* stream, rsst_handle* out) {
   if (!out) return RSST_E_ARG;

@@ -109,19 +109,26 @@ __device__ __forceinline__ double stage_body3(const StageArgs& A, double* lds, i
   double* const yf = FY + r * (NV * NXP) + i_raw;   // written by thread-row r + 1 (slot r); r reads it
   double* const xs = FXS + rl * (NV * NWXC) + wx;   // + c NV NWXC + v NWXC
 
-  // FP32 perturbation form: the background in registers.  Along z: bgA holds
-  // plane k and bgB plane k + 2, loaded at the top of each plane; otherwise
-  // (uniform, along x, along y) bgA holds the lower cell's values for the
-  // whole march.  With a profile along y the upper cell and the rows outside
-  // the tile take the indexed path (loads where used).
+  // FP32 perturbation form: the background is loaded where it is used, not
+  // held across the march (ten FP64 values per plane would take 40 VGPRs).
+  // bg_at(kk, b): the lower cell's background at plane kk.  Uniform or along
+  // z, its index is the same for the whole workgroup and the load goes
+  // through the scalar cache into SGPRs; along x it is the thread's column
+  // (vector loads, L1 hits).  With a profile along y the upper cell and the
+  // rows outside the tile take the indexed path.
   const bool bg_on_m = F32 && A.bg_axis == 2;
   const bool bg_rows = F32 && A.bg_axis == 1;
   auto bg_cell = [&](int c) { return A.bg_axis == 0 ? i : (A.bg_axis == 1 ? jl + c : 0); };
-  double bgA[NV], bgB[NV];
   const __amdgpu_buffer_rsrc_t bgr = field_rsrc(A.bg, F32 ? (long long)NV * A.nbg * 8 : 0);
-  if constexpr (F32) {
-    if (!bg_on_m) load_bg<NV>(bgr, A.nbg, A.bg_uniform ? 0 : bg_cell(0), bgA);
-  }
+  auto bg_at = [&](int kk, double (&b)[NV]) {
+    if (A.bg_uniform) {
+      const int u = __builtin_amdgcn_readfirstlane(A.bg_axis == 2 ? kk : 0);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) b[v] = A.bg[v * A.nbg + u];
+    } else {
+      load_bg<NV>(bgr, A.nbg, bg_cell(0), b);
+    }
+  };
   // FP64 state of stored values: FP32, with the background at profile index b
   // (vector loads where used); FP64, with the mirror sign and the hydrostatic
   // wall's carried pressure (lever)
@@ -192,10 +199,17 @@ __device__ __forceinline__ double stage_body3(const StageArgs& A, double* lds, i
   const int ob1 = o_lo ? blo1 : bhi1, ob2 = o_lo ? blo2 : bhi2;
   const double ol1 = o_lo ? llo1 : lhi1, ol2 = o_lo ? llo2 : lhi2;
   ST o1[NV], o2[NV], o3[ONE ? NV : 1], o4[ONE ? NV : 1];  // stored values, finished at use
-  // an outside row's FP64 state at plane k
+  // an outside row's FP64 state at plane k (k_cur: the plane of this
+  // iteration)
+  int k_cur = 0;
   auto fin_out = [&](const ST (&raw)[NV], int neg, int b, double lev, double (&u)[NV]) {
-    if (F32 && !bg_rows) finish_cell_bgv<NDIM, ST>(raw, neg, bgA, u);
-    else fin_idx(raw, neg, b, lev, u);
+    if (F32 && !bg_rows) {
+      double bz[NV];
+      bg_at(k_cur, bz);
+      finish_cell_bgv<NDIM, ST>(raw, neg, bz, u);
+    } else {
+      fin_idx(raw, neg, b, lev, u);
+    }
   };
 
   double q0[2][NV], q1[2][NV], sm0[2][NV], Fm_lo[2][NV];
@@ -246,12 +260,7 @@ __device__ __forceinline__ double stage_body3(const StageArgs& A, double* lds, i
     const int q2k = map_index(k + 2, G.nm, rm_lo, rm_hi, q2n);
     const int q2neg = q2n ? NDIM : -1;
     const double q2lev = HYD ? hydro_lever(k + 2, G.nm, rm_lo, rm_hi, A.dx[2], A.g[2]) : 0.0;
-    if constexpr (F32) {
-      if (bg_on_m) {
-        load_bg<NV>(bgr, A.nbg, k, bgA);
-        load_bg<NV>(bgr, A.nbg, q2k, bgB);
-      }
-    }
+    k_cur = k;
 #pragma unroll
     for (int c = 0; c < 2; ++c) load_cell_raw<NDIM, ST>(uin, q2k, colc[c], q2r[c]);
 
@@ -429,8 +438,9 @@ __device__ __forceinline__ double stage_body3(const StageArgs& A, double* lds, i
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       if constexpr (F32) {
-        if (bg_on_m) fin_c(q2r[c], q2neg, c, bgB, q2[c]);
-        else fin_c(q2r[c], q2neg, c, bgA, q2[c]);
+        double bz[NV];
+        bg_at(q2k, bz);
+        fin_c(q2r[c], q2neg, c, bz, q2[c]);
       } else {
         fin_idx(q2r[c], q2neg, 0, q2lev, q2[c]);
       }
@@ -452,7 +462,9 @@ __device__ __forceinline__ double stage_body3(const StageArgs& A, double* lds, i
       double un[NV];
       if constexpr (STAGE == 2) {
         if constexpr (F32) {
-          fin_c(unr[c], -1, c, bgA, un);
+          double bz[NV];
+          bg_at(k, bz);
+          fin_c(unr[c], -1, c, bz, un);
         } else {
           fin_idx(unr[c], -1, 0, 0.0, un);
         }
@@ -461,9 +473,8 @@ __device__ __forceinline__ double stage_body3(const StageArgs& A, double* lds, i
         bad |= b;
         double out[NV], bgc[NV];
         if constexpr (F32) {
-#pragma unroll
-          for (int v = 0; v < NV; ++v) bgc[v] = bgA[v];
           if (c == 1 && bg_rows) load_bg<NV>(bgr, A.nbg, jl + 1, bgc);
+          else bg_at(k, bgc);
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
