@@ -28,3 +28,14 @@ def test_rt_initial_state():
     assert np.allclose(P[:, 0], P[:, 5]) and P[0, 0] > P[-1, 0] > 1000.0
     # light below, heavy above, 1% perturbation along x
     assert U[0][0].mean() < 1.01 and U[0][-1].mean() > 9.9
+
+
+def test_rt_strip_needs_a_face_at_one_eighth():
+    """The Sec. 4.4 strip starts at x = 1/8, which is a cell face only when
+    n is a multiple of 8; its grid is n/4 x n with mirror walls in x."""
+    import pytest
+    with pytest.raises(ValueError):
+        W.rt2d(36, strip=True)
+    cfg, U0, meta = W.rt2d(32, strip=True)
+    assert cfg["n"][:2] == [8, 32] and U0.shape == (4, 32, 8)
+    assert cfg["bc_lo"][0] == cfg["bc_hi"][0] == "reflect" and meta["x0"] == 0.125
